@@ -1,0 +1,228 @@
+/*
+ * rhg.h -- C ABI of the MI355X (gfx950) threshold random hyperbolic graph
+ * generator.
+ *
+ * The method is the band-based neighbour query of von Looz, Oezdayi, Laue,
+ * Meyerhenke, "Generating massive complex networks with hyperbolic geometry
+ * faster in practice" (HPEC 2016), Sec. III, Algorithm 1:
+ *   - n points in a hyperbolic disk of radius R, angle uniform, radius with
+ *     density alpha sinh(alpha r)/(cosh(alpha R) - 1)  (Sec. II, Eq. 1);
+ *   - edge {u, v} iff dist_H(u, v) < R, dist_H by the hyperbolic law of
+ *     cosines (Sec. II, Eq. 3);
+ *   - R from the average degree by getTargetRadius (Sec. III-B), or given;
+ *   - the disk is cut in ring slabs with geometric widths (Sec. III-A,
+ *     Eq. 4), each slab angle-sorted, and every point scans the angular
+ *     window of each slab outward of it (getMinMaxPhi, Sec. III-B).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns rhg_status (0 = RHG_OK, negative = error) unless it
+ *     returns void.  No call aborts the process; invalid arguments give
+ *     RHG_EINVAL and leave outputs untouched.
+ *   - Device pointers are HIP device addresses on the context's device; host
+ *     pointers are ordinary process memory.  Each argument says which.
+ *   - Output edges are int32 pairs (lo, hi), lo < hi, in the original point
+ *     indices (the sampler's index i, or the position in the caller's
+ *     coordinate arrays).  Each undirected edge appears exactly once, no
+ *     self loops.  The order is deterministic for given inputs and library
+ *     build but otherwise unspecified: compare edge lists as sets.
+ *   - The distance test is evaluated in IEEE binary64 in a fixed order
+ *     (cosh(r_u - r_v) + 2 sinh r_u sinh r_v sin^2(dtheta/2), from per-point
+ *     exp(r), exp(-r), sinh r, sin(theta/2), cos(theta/2)), strict "< cosh R".
+ *     RHG_FP32_RECHECK decides the same predicate with an FP32 filter and a
+ *     proven margin and re-decides the undecided pairs in FP64: its edge set
+ *     is identical to RHG_FP64's.
+ *   - One context = one HIP stream; a context is not thread safe.  A server
+ *     (rhg_server_*) is thread safe.
+ */
+#ifndef RHG_H
+#define RHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RHG_OK = 0,
+    RHG_EINVAL = -1,  /* invalid argument (range, NaN, NULL, unreachable average degree) */
+    RHG_ENOMEM = -2,  /* device or host allocation failed */
+    RHG_EDEVICE = -3, /* HIP runtime error (no device, launch failure) */
+    RHG_ERANGE = -4,  /* size beyond what the int32 output or internal counters can hold */
+    RHG_ETRUNC = -5,  /* caller buffer smaller than the result */
+    RHG_EBUSY = -6    /* server: result not ready (non-blocking wait) */
+} rhg_status;
+
+typedef enum {
+    RHG_FP64 = 0,         /* distance test in FP64 */
+    RHG_FP32_RECHECK = 1  /* FP32 filter with margin, undecided pairs in FP64; same edges */
+} rhg_precision;
+
+/* Generation parameters (Algorithm 1 input: n, average degree, alpha = (gamma-1)/2).
+ *   n          number of points, 2 <= n < 2^31.
+ *   alpha      dispersion, > 0; with kbar (R <= 0) it must be > 1/2.
+ *   kbar       target average degree, used when R <= 0: R = getTargetRadius(n, alpha, kbar).
+ *   R          disk radius; R > 0 overrides kbar.  FP32_RECHECK needs R <= 43.
+ *   seed       SplitMix64 seed; point i uses outputs 2i (angle) and 2i+1 (radius).
+ *   precision  RHG_FP64 or RHG_FP32_RECHECK.
+ *   num_bands  number of slabs B, 0 = ceil(log2 n); 1 <= B <= 32.
+ *   band_ratio width ratio p of consecutive slabs, 0 = 0.9; 0 < p <= 1 (p = 1: equal widths). */
+typedef struct {
+    uint64_t n;
+    double alpha;
+    double kbar;
+    double R;
+    uint64_t seed;
+    rhg_precision precision;
+    uint32_t num_bands;
+    double band_ratio;
+} rhg_params;
+
+typedef struct rhg_ctx rhg_ctx;
+typedef struct rhg_graph rhg_graph;
+typedef struct rhg_server rhg_server;
+
+/* Per-graph counters and phase times.
+ *   edges       m
+ *   candidates  distance tests performed (window sizes summed)
+ *   rechecks    pairs the FP32 filter left undecided (FP32_RECHECK only)
+ *   windows     (query, slab) windows planned
+ *   ms[8]       device time per phase from HIP events on the context stream:
+ *               0 sample+band keys, 1 sort, 2 table+slab index, 3 window plan,
+ *               4 count, 5 scans, 6 emit, 7 total (first to last event)
+ *   bytes_moved algorithmic HBM bytes of phases 1-6 (reads + writes the
+ *               method needs), for roofline reporting */
+typedef struct {
+    uint64_t edges;
+    uint64_t candidates;
+    uint64_t rechecks;
+    uint64_t windows;
+    uint64_t disagreements; /* FP32 decisions differing from FP64 (exhaustive option only; must be 0) */
+    double ms[8];
+    uint64_t bytes_moved;
+} rhg_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run
+ * on (e.g. the caller's PyTorch stream), or NULL for a library-owned stream.
+ * The context keeps device work buffers between calls (grown as needed). */
+rhg_status rhg_ctx_create(int device, void *hip_stream, rhg_ctx **out);
+
+/* Route the context's device allocations through the caller (e.g. a caching
+ * allocator).  alloc(bytes, user) returns a device pointer or NULL; free(ptr,
+ * user).  Pass alloc = NULL to restore hipMalloc/hipFree.  Must be called
+ * before the first generation on the context. */
+rhg_status rhg_ctx_set_allocator(rhg_ctx *ctx, void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *),
+                                 void *user);
+
+/* Context options.
+ *   RHG_OPT_FP32_EXHAUSTIVE (value 0/1): in RHG_FP32_RECHECK count passes also
+ *   evaluate the FP64 test on every candidate the filter decided and count
+ *   disagreements into rhg_stats.disagreements (a self-check of the margin;
+ *   slower). */
+typedef enum { RHG_OPT_FP32_EXHAUSTIVE = 1 } rhg_option;
+rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value);
+
+/* Release the context and its work buffers (graphs stay valid). */
+void rhg_ctx_destroy(rhg_ctx *ctx);
+
+/* ---- parameters (host only, no device use) ------------------------------ */
+
+/* getTargetRadius (Sec. III-B): the R on the decreasing branch of the
+ * average-degree approximation with zeta = 1 that equals kbar.
+ * RHG_EINVAL if alpha <= 1/2, kbar <= 0, n < 2, non-finite input, or kbar
+ * above the approximation's maximum. */
+rhg_status rhg_target_radius(uint64_t n, double alpha, double kbar, double *R_out);
+
+/* Slab boundaries c_0 = 0 < ... < c_B = R (Sec. III-A, Eq. 4) as used by the
+ * library; c_out holds B+1 doubles (host). */
+rhg_status rhg_band_boundaries(double R, uint32_t num_bands, double band_ratio, double *c_out);
+
+/* ---- generation ----------------------------------------------------------- */
+
+/* Sample n points (Eq. 1) from params->seed on the device and return the
+ * threshold RHG (Algorithm 1).  *out receives a library-owned graph whose
+ * edges stay in device memory until rhg_graph_free. */
+rhg_status rhg_generate(rhg_ctx *ctx, const rhg_params *params, rhg_graph **out);
+
+/* Same for caller coordinates: theta[n] in [0, 2pi] (2pi meaning fl(2*pi)),
+ * r[n] in [0, R], FP64, host or device memory (coords_on_device = 0/1; device
+ * arrays are only read).  Edges use the positions in these arrays. */
+rhg_status rhg_generate_from_coords(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r, double R,
+                                    rhg_precision precision, int coords_on_device, rhg_graph **out);
+
+/* Same, with the per-point table supplied instead of computed on the device:
+ * table5xn = [exp(r) | exp(-r) | sinh r | sin(theta/2) | cos(theta/2)], each
+ * n doubles, row-major (5 x n), same memory kind as theta/r.  The distance
+ * test reads exactly these bits, so any caller-side evaluation of the same
+ * table gives a bit-identical edge set.  theta and r still place points in
+ * slabs and windows. */
+rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
+                                   const double *table5xn, double R, rhg_precision precision, int on_device,
+                                   rhg_graph **out);
+
+/* Two-phase form for caller-owned output (e.g. a PyTorch tensor):
+ * rhg_count plans and counts (m), rhg_emit writes the m pairs into
+ * dev_pairs (device, >= 2*m int32, capacity_pairs in pairs; RHG_ETRUNC if
+ * smaller, nothing written).  *plan is a graph handle without edges; free it
+ * with rhg_graph_free.  rhg_emit may be called once per plan. */
+rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_graph **plan, uint64_t *m);
+rhg_status rhg_emit(rhg_ctx *ctx, rhg_graph *plan, int32_t *dev_pairs, uint64_t capacity_pairs);
+
+/* ---- graph handle --------------------------------------------------------- */
+
+rhg_status rhg_graph_num_edges(const rhg_graph *g, uint64_t *m);
+rhg_status rhg_graph_num_points(const rhg_graph *g, uint64_t *n);
+rhg_status rhg_graph_radius(const rhg_graph *g, double *R);
+
+/* Borrowed device pointer to the 2*m int32 edge array; valid until
+ * rhg_graph_free.  RHG_EINVAL for a count-only plan before rhg_emit. */
+rhg_status rhg_graph_edges_device(const rhg_graph *g, const int32_t **pairs);
+
+/* Copy the edges to host memory host_pairs (capacity_pairs pairs);
+ * RHG_ETRUNC (nothing copied) if capacity_pairs < m. */
+rhg_status rhg_graph_copy_edges(const rhg_graph *g, int32_t *host_pairs, uint64_t capacity_pairs);
+
+/* Copy the points and the exact table bits the distance test used, in
+ * original point order, to host memory: theta[n], r[n], table5xn[5*n]
+ * (layout as in rhg_generate_from_table); any pointer may be NULL to skip it.
+ * K receives cosh R as used.  Only graphs from rhg_generate/rhg_count keep
+ * the points; for the coordinate forms this returns what was passed. */
+rhg_status rhg_graph_copy_points(const rhg_graph *g, double *theta, double *r, double *table5xn, double *K);
+
+rhg_status rhg_graph_stats(const rhg_graph *g, rhg_stats *stats);
+
+/* Release a graph or plan and its device memory.  NULL is ignored. */
+void rhg_graph_free(rhg_graph *g);
+
+/* ---- serving --------------------------------------------------------------- */
+
+/* A request server on one device: submitted generation requests are admitted
+ * while their estimated edge memory (n * kbar / 2 pairs, 8 bytes each, plus
+ * per-point work memory) fits in mem_budget_bytes; admitted requests run
+ * concurrently on several streams, small ones packed together into shared
+ * launches; results are identical to rhg_generate's for the same params. */
+rhg_status rhg_server_create(int device, uint64_t mem_budget_bytes, rhg_server **out);
+/* Queue a request (params copied).  Returns at once with a ticket. */
+rhg_status rhg_server_submit(rhg_server *s, const rhg_params *params, uint64_t *ticket);
+/* Wait for a ticket: blocks until done (timeout_ms < 0), or waits at most
+ * timeout_ms and returns RHG_EBUSY if not done.  *out receives the graph
+ * (caller frees it); latency_ms the time from submit to device completion.
+ * A request that failed returns its error here. */
+rhg_status rhg_server_wait(rhg_server *s, uint64_t ticket, int timeout_ms, rhg_graph **out, double *latency_ms);
+/* Stop accepting, finish or fail pending requests, release everything. */
+void rhg_server_destroy(rhg_server *s);
+
+/* Static string for a status code. */
+const char *rhg_status_str(rhg_status s);
+
+/* Library version string (for determinism claims: same inputs + same version -> same bytes). */
+const char *rhg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHG_H */

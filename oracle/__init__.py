@@ -68,6 +68,8 @@ def lib():
         L.orc_is_edge.argtypes = [vp, vp, vp, vp, vp, i64, i64, d]
         L.orc_brute.restype = i64
         L.orc_brute.argtypes = [i64, vp, vp, vp, vp, vp, d, ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_brute_rows.restype = i64
+        L.orc_brute_rows.argtypes = [i64, vp, vp, vp, vp, vp, d, vp, i64, i32, ctypes.POINTER(ctypes.c_void_p)]
         L.orc_window.restype = i32
         L.orc_window.argtypes = [d, d, d, pd]
         L.orc_band_sweep.restype = i64
@@ -170,6 +172,18 @@ def brute(tab: np.ndarray, K: float) -> np.ndarray:
     p = ctypes.c_void_p()
     m = lib().orc_brute(tab.shape[1], _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]), _ptr(tab[4]),
                         float(K), ctypes.byref(p))
+    return _take(p, m)
+
+
+def brute_rows(tab: np.ndarray, K: float, queries, threads: int = 0) -> np.ndarray:
+    """For each listed query q, all (q, w) with w != q and coshdist < K (all-pairs definition on those rows)."""
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    q = np.ascontiguousarray(queries, dtype=np.int64)
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    p = ctypes.c_void_p()
+    m = lib().orc_brute_rows(tab.shape[1], _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]), _ptr(tab[4]),
+                             float(K), _ptr(q), len(q), int(threads), ctypes.byref(p))
     return _take(p, m)
 
 

@@ -250,6 +250,85 @@ int64_t orc_brute(int64_t n, const double *ep, const double *em, const double *s
 }
 
 /* ------------------------------------------------------------------------- */
+/* Brute force for selected rows: all neighbours w of each listed query q    */
+/* (the plain definition restricted to pairs touching q).  Output pairs are */
+/* (q, w) in query-list order then increasing w; threads split the queries. */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n, nq;
+    const int64_t *q;
+    orc_tab tab;
+    double K;
+    volatile int64_t next;
+    orc_buf *bufs;
+} orc_rows_ctx;
+
+static void *orc_rows_worker(void *arg) {
+    orc_rows_ctx *X = (orc_rows_ctx *)arg;
+    for (;;) {
+        int64_t k = __sync_fetch_and_add(&X->next, 1);
+        if (k >= X->nq) break;
+        int64_t v = X->q[k];
+        orc_buf *b = &X->bufs[k];
+        for (int64_t w = 0; w < X->n; ++w) {
+            if (w == v) continue;
+            if (orc_V(&X->tab, v, w) < X->K) {
+                /* store (v, w) unordered: the row's own view */
+                if (b->m == b->cap) {
+                    int64_t nc = b->cap ? 2 * b->cap : 256;
+                    int32_t *np = (int32_t *)realloc(b->p, (size_t)nc * 2 * sizeof(int32_t));
+                    if (!np) { b->oom = 1; break; }
+                    b->p = np;
+                    b->cap = nc;
+                }
+                b->p[2 * b->m] = (int32_t)v;
+                b->p[2 * b->m + 1] = (int32_t)w;
+                b->m++;
+            }
+        }
+    }
+    return NULL;
+}
+
+int64_t orc_brute_rows(int64_t n, const double *ep, const double *em, const double *sh, const double *hs,
+                       const double *hc, double K, const int64_t *queries, int64_t nq, int nthreads,
+                       int32_t **out) {
+    *out = NULL;
+    orc_rows_ctx X;
+    memset(&X, 0, sizeof X);
+    X.n = n; X.nq = nq; X.q = queries; X.K = K; X.next = 0;
+    X.tab.ep = ep; X.tab.em = em; X.tab.sh = sh; X.tab.hs = hs; X.tab.hc = hc;
+    X.bufs = (orc_buf *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(orc_buf));
+    if (!X.bufs) return -1;
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    int started = 0;
+    if (th) {
+        for (int t = 0; t < nthreads; ++t)
+            if (pthread_create(&th[t], NULL, orc_rows_worker, &X) == 0) ++started;
+        for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+        free(th);
+    }
+    if (started == 0) orc_rows_worker(&X);
+    int64_t m = 0;
+    int oom = 0;
+    for (int64_t k = 0; k < nq; ++k) { m += X.bufs[k].m; oom |= X.bufs[k].oom; }
+    int32_t *all = oom ? NULL : (int32_t *)malloc((size_t)(m > 0 ? m : 1) * 2 * sizeof(int32_t));
+    if (all) {
+        int64_t at = 0;
+        for (int64_t k = 0; k < nq; ++k) {
+            if (X.bufs[k].m) memcpy(all + 2 * at, X.bufs[k].p, (size_t)X.bufs[k].m * 2 * sizeof(int32_t));
+            at += X.bufs[k].m;
+        }
+    }
+    for (int64_t k = 0; k < nq; ++k) free(X.bufs[k].p);
+    free(X.bufs);
+    if (!all) return -1;
+    *out = all;
+    return m;
+}
+
+/* ------------------------------------------------------------------------- */
 /* getMinMaxPhi (Sec. III-B).  For query radius rv and slab inner boundary c, */
 /* every neighbour w of v in the slab satisfies                               */
 /*   cos|phi_w - phi_v| >= (cosh rv cosh c - cosh R) / (sinh rv sinh c).      */

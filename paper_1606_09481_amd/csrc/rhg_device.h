@@ -1,0 +1,154 @@
+// rhg_device.h -- device-side definitions of the gfx950 threshold RHG generator.
+//
+// Layout of one generation in HBM (n points, B slabs, all arrays in the
+// slab-major, angle-sorted order produced by the sort):
+//   keys[n]   u32  (slab << 27) | q(theta): q is a monotone 27-bit
+//                  quantisation of the angle; the sort key and the search key
+//   idx[n]    u32  original point index of each sorted position
+//   th[n], rr[n]                         f64 angle and radius
+//   ep[n], em[n], sh[n], hs[n], hc[n]    f64 exp(r), exp(-r), sinh r,
+//                                        sin(theta/2), cos(theta/2)
+//   ep32[n], em32[n], sh32[n]            f32 shadows of ep, em, sh
+//   btab[]    u32  per slab j, 2^bits_j + 1 bucket starts over the top bits
+//                  of q (a direct-mapped index into the sorted slab)
+//   win[]     uint2 per (query, slab j >= slab(query)): circular position
+//                  window (start, count) in slab j
+//   per 64-query batch: candidate totals and work units; per unit: edges.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rhgd {
+
+constexpr int MAX_BANDS = 32;
+constexpr int QBITS = 27;
+constexpr uint32_t QMASK = (1u << QBITS) - 1u;
+constexpr uint32_t QHALF = 1u << (QBITS - 1);     // half a turn in key units
+constexpr double TWO_PI = 6.283185307179586;     // fl(2 pi), the angle period of the sampler
+constexpr double HALF_PI = 1.5707963267948966;
+constexpr double QSCALE = 134217728.0 / TWO_PI;  // 2^27 / fl(2 pi)
+constexpr int WAVE = 64;
+constexpr int BATCH = 64;        // queries per batch (one wavefront)
+constexpr uint32_t UNIT = 4096;  // candidates per work unit (upper bound)
+
+enum SrcMode { SRC_SEED = 0, SRC_COORDS = 1, SRC_TABLE = 2 };
+
+// Where the points come from.
+struct Source {
+    int mode;
+    uint64_t n;
+    uint64_t seed;
+    double alpha, R;
+    double sinh_half_aR;    // sinh(alpha R / 2), host libm
+    const double *theta, *r;  // SRC_COORDS / SRC_TABLE (device)
+    const double *table;      // SRC_TABLE: 5 x n (device)
+};
+
+// Everything the window plan and the query kernels read.
+struct Geo {
+    uint32_t n;
+    int B;
+    double R, K, Kw;          // cosh R and the widened threshold used for windows
+    float klo32, khi32;       // FP32 filter thresholds (round-down / round-up of K(1 -+ mu))
+    double c[MAX_BANDS + 1];  // slab boundaries
+    double shc[MAX_BANDS + 1];  // sinh c_j
+    uint32_t bs[MAX_BANDS + 1]; // slab start positions, bs[B] = n
+    uint64_t winbase[MAX_BANDS + 1];
+    uint32_t bto[MAX_BANDS + 1];  // bucket table offset of slab j
+    int bshift[MAX_BANDS + 1];    // q >> bshift -> bucket
+    const uint32_t *keys, *idx;
+    const double *th, *rr, *ep, *em, *sh, *hs, *hc;
+    const float *ep32, *em32, *sh32;
+    const uint32_t *btab;
+};
+
+__device__ __forceinline__ uint32_t qang(double x) {
+    double y = x * QSCALE;
+    if (!(y > 0.0)) return 0u;
+    if (y >= 134217727.0) return QMASK;
+    return (uint32_t)y;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): k-th output of the generator seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Point i of the seeded model (Eq. 1): angle uniform on [0, 2pi), radius by
+// inverting F(r) = sinh^2(alpha r/2)/sinh^2(alpha R/2).
+__device__ __forceinline__ void sample_point(const Source &s, uint64_t i, double &theta, double &r) {
+    uint64_t x1 = splitmix64(s.seed, 2ull * i);
+    uint64_t x2 = splitmix64(s.seed, 2ull * i + 1ull);
+    double u1 = (double)(x1 >> 11) * 0x1p-53;
+    double u2 = (double)(x2 >> 11) * 0x1p-53;
+    theta = u1 * TWO_PI;
+    double rv = 2.0 * asinh(sqrt(u2) * s.sinh_half_aR) / s.alpha;
+    r = rv > s.R ? s.R : rv;
+}
+
+__device__ __forceinline__ void load_point(const Source &s, uint64_t i, double &theta, double &r) {
+    if (s.mode == SRC_SEED) {
+        sample_point(s, i, theta, r);
+    } else {
+        theta = s.theta[i];
+        r = s.r[i];
+    }
+}
+
+// Per-point values the distance test reads.
+__device__ __forceinline__ void point_table(const Source &s, uint64_t i, double theta, double r, double &ep,
+                                            double &em, double &sh, double &hs, double &hc) {
+    if (s.mode == SRC_TABLE) {
+        ep = s.table[i];
+        em = s.table[s.n + i];
+        sh = s.table[2 * s.n + i];
+        hs = s.table[3 * s.n + i];
+        hc = s.table[4 * s.n + i];
+    } else {
+        ep = exp(r);
+        em = exp(-r);
+        sh = sinh(r);
+        hs = sin(theta * 0.5);
+        hc = cos(theta * 0.5);
+    }
+}
+
+// ---- wavefront primitives ------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    const int l = (int)lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = __shfl_up(x, d, 64);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_bcast_u32(uint32_t x, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+
+}  // namespace rhgd

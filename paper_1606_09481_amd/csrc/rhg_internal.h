@@ -1,0 +1,104 @@
+// rhg_internal.h -- host-side structures behind the C ABI (library internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/rhg.h"
+#include "rhg_device.h"
+#include "rhg_kernels.h"
+
+namespace rhgi {
+
+enum Slot {
+    S_KEYS, S_VALS, S_KEYS2, S_VALS2, S_HIST, S_SORTSCR,
+    S_TH, S_RR, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
+    S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
+    S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2,
+    S_COUNT
+};
+
+enum Ev { EV_KEYS0, EV_KEYS1, EV_SORT0, EV_SORT1, EV_TABLE1, EV_PLAN1, EV_COUNT0, EV_COUNT1, EV_SCAN1,
+          EV_EMIT0, EV_EMIT1, EV_COUNT_ };
+
+struct SlotBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_user = nullptr;
+    SlotBuf slots[S_COUNT];
+    hipEvent_t ev[EV_COUNT_] = {};
+    void *pinned = nullptr;  // 4 KB host readback area
+    int exhaustive = 0;
+    uint64_t generation = 0;  // bumped by every count; a plan may emit only while current
+
+    void *dev_alloc(size_t bytes);
+    void dev_free(void *p);
+    void *buf(int slot, size_t bytes);  // grow-only work buffer
+    ~Ctx();
+};
+
+// What to generate.
+struct Request {
+    int mode = rhgd::SRC_SEED;
+    uint64_t n = 0;
+    double alpha = 1.0, R = 0.0;
+    uint64_t seed = 0;
+    int precision = RHG_FP64;
+    uint32_t num_bands = 0;
+    double band_ratio = 0.0;
+    const double *theta = nullptr, *r = nullptr, *table = nullptr;
+    int on_device = 0;
+};
+
+// One planned generation.
+struct Plan {
+    uint64_t n = 0;
+    int B = 1;
+    double p = 0.9;
+    double R = 0, K = 0;
+    double c[rhgd::MAX_BANDS + 1] = {};
+    bool fp32 = false;
+    rhgd::Geo geo;
+    rhgk::QueryArgs qa;
+    uint64_t n_units = 0, windows = 0, candidates = 0, m = 0, rechecks = 0, disagreements = 0;
+    uint64_t generation = 0;
+    bool emitted = false;
+    double ms[8] = {};
+};
+
+struct Graph {
+    int device = 0;
+    Ctx *ctx = nullptr;  // context that planned it (count-only plans emit through it)
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_user = nullptr;
+    Request rq;
+    Plan pl;
+    int32_t *edges = nullptr;
+    double *d_theta = nullptr, *d_r = nullptr, *d_table = nullptr;
+};
+
+// Algorithmic HBM bytes of the timed path (sort through emit), the traffic
+// the method itself needs: per point the key and index written and read
+// once per sort digit pass, the table (7 x 8 B) written once and read by the
+// plan and by both query passes, per window 8 B written and read twice, per
+// edge one 8-byte pair written.
+inline uint64_t algorithmic_bytes(const Plan &p) {
+    const uint64_t n = p.n;
+    const uint64_t per_point = 8ull * 2 * 4 + 56 + 5 * 8 * 3;
+    return n * per_point + p.windows * 8 * 3 + p.m * 8;
+}
+
+rhg_status describe(const Request &rq, Plan &pl);
+rhg_status run_count(Ctx *c, const Request &rq, Plan &pl);
+rhg_status run_emit(Ctx *c, Plan &pl, int2 *out);
+rhg_status generate(Ctx *c, const Request &rq, bool emit, Graph **out, uint64_t *m_out);
+
+}  // namespace rhgi

@@ -1,0 +1,67 @@
+// rhg_kernels.h -- host-side launchers of the gfx950 kernels (library internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rhg_device.h"
+
+namespace rhgk {
+
+// a0 + a2: sample or read each point, find its slab (c_i <= r < c_{i+1},
+// r = R in the last), build the sort key (slab << 27 | q(theta)) and the
+// identity payload; count points per slab into hist[B] (zeroed here);
+// err |= 1 on a coordinate outside [0, 2pi] x [0, R] or non-finite.
+void keys(const rhgd::Source &src, int B, const double *c_host, uint32_t *keys, uint32_t *vals, uint32_t *hist,
+          int *err, hipStream_t st);
+
+// a3: stable LSD radix sort of (keys, vals), `bits` low key bits, 8 per pass;
+// the result ends in (keys, vals); tmp buffers of n each; scratch from
+// sort_scratch_bytes.
+size_t sort_scratch_bytes(uint64_t n);
+void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
+                int bits, hipStream_t st);
+
+// a1 + a3 gather: per sorted position, the point's angle, radius and table
+// (computed, or copied from the caller's table) in sorted order.
+void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double *rr, double *ep,
+            double *em, double *sh, double *hs, double *hc, float *ep32, float *em32, float *sh32, hipStream_t st);
+
+// Same values in original order (for exporting the exact bits used).
+void point_values(const rhgd::Source &src, uint64_t n, double *th, double *rr, double *table5xn, hipStream_t st);
+
+// Slab bucket index: btab (geo.bto / geo.bshift layout).
+void bucket_index(const rhgd::Geo &geo, uint32_t *btab, hipStream_t st);
+
+// a4: windows of every (query, slab >= slab(query)); per-batch candidate totals.
+void plan(const rhgd::Geo &geo, uint2 *win, uint64_t *batch_cand, hipStream_t st);
+
+// a6 scans: out[0..len] = exclusive prefix of in[0..len) (out[len] = total).
+size_t scan_scratch_bytes(uint64_t len);
+void scan_u64(const uint64_t *in, uint64_t *out, uint64_t len, void *scratch, hipStream_t st);
+void scan_u32(const uint32_t *in, uint64_t *out, uint64_t len, void *scratch, hipStream_t st);
+
+// Work units: units per batch = ceil(cand / UNIT).
+void units_per_batch(const uint64_t *batch_cand, uint64_t nb, uint64_t *nunits, hipStream_t st);
+void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint32_t *unit_batch, hipStream_t st);
+
+// a5 / a7 / a8: the band query.  count: edges per unit into unit_edges,
+// stats[0] += rechecks, stats[1] += filter/FP64 disagreements (exhaustive).
+// emit: pairs at unit_off_edges[u].
+struct QueryArgs {
+    rhgd::Geo geo;
+    const uint2 *win;
+    const uint64_t *batch_cand;
+    const uint64_t *unit_off;   // per batch, first unit (exclusive scan of units)
+    const uint32_t *unit_batch;
+    uint64_t n_units;
+    uint32_t *unit_edges;          // count
+    const uint64_t *unit_edge_off; // emit
+    int2 *out;                     // emit
+    uint64_t out_capacity;         // emit: pairs available at out
+    unsigned long long *stats;     // count: [rechecks, disagreements]
+    int exhaustive;
+};
+void query_count(const QueryArgs &a, int fp32, hipStream_t st);
+void query_emit(const QueryArgs &a, int fp32, hipStream_t st);
+
+}  // namespace rhgk

@@ -1,0 +1,737 @@
+// runtime.cpp -- C ABI of the threshold RHG generator: parameters, contexts,
+// device buffers, phase orchestration and graph handles.
+//
+// One generation (Algorithm 1) on the context stream:
+//   keys (sample/read points, slab, sort key) -> [sync: slab sizes]
+//   -> radix sort -> gather table -> slab bucket index -> window plan
+//   -> batch scan -> units -> [sync: unit count] -> count -> unit scan
+//   -> [sync: m] -> emit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rhg.h"
+#include "rhg_internal.h"
+#include "rhg_kernels.h"
+
+using namespace rhgd;
+
+// ---------------------------------------------------------------------------
+// Parameters (host only)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Average-degree approximation (Sec. III-B) with zeta = 1:
+//   kbar(R) = (2/pi) xi^2 n [ e^{-R/2} + e^{-alpha R} (alpha R/2 (pi/4 a^-2 - (pi-1) a^-1 + (pi-2)) - 1) ],
+// xi = alpha / (alpha - 1/2), a = alpha.
+double kbar_of_R(double n, double alpha, double R) {
+    const double pi = M_PI;
+    const double xi = alpha / (alpha - 0.5);
+    const double inv = 1.0 / alpha;
+    const double poly = (pi / 4.0) * inv * inv - (pi - 1.0) * inv + (pi - 2.0);
+    return (2.0 / pi) * xi * xi * n * (std::exp(-R / 2.0) + std::exp(-alpha * R) * (alpha * R / 2.0 * poly - 1.0));
+}
+
+}  // namespace
+
+extern "C" rhg_status rhg_target_radius(uint64_t n, double alpha, double kbar, double *R_out) {
+    if (!R_out || n < 2 || !std::isfinite(alpha) || !std::isfinite(kbar) || !(alpha > 0.5) || !(kbar > 0.0))
+        return RHG_EINVAL;
+    const double nd = (double)n;
+    // Walk left from a radius where the approximation is below kbar; the
+    // function rises towards its single maximum, so the first point at or
+    // above kbar brackets the root of the decreasing branch.
+    const double xi = alpha / (alpha - 0.5);
+    double hi = std::max(1.0, 2.0 * std::log((2.0 / M_PI) * xi * xi * nd / kbar) + 4.0);
+    for (int k = 0; k < 4096 && kbar_of_R(nd, alpha, hi) >= kbar; ++k) hi += 1.0;
+    if (kbar_of_R(nd, alpha, hi) >= kbar) return RHG_EINVAL;
+    double lo = hi, prev = kbar_of_R(nd, alpha, hi);
+    for (;;) {
+        double x = lo - 0.125;
+        if (x <= 0.0) return RHG_EINVAL;
+        double f = kbar_of_R(nd, alpha, x);
+        if (f >= kbar) { lo = x; break; }
+        if (f < prev) return RHG_EINVAL;  // past the maximum without reaching kbar
+        prev = f;
+        hi = x;
+        lo = x;
+    }
+    // bisection to adjacent doubles: f(lo) >= kbar > f(hi)
+    for (int it = 0; it < 2000; ++it) {
+        double mid = lo + (hi - lo) / 2.0;
+        if (mid <= lo || mid >= hi) break;
+        if (kbar_of_R(nd, alpha, mid) >= kbar) lo = mid; else hi = mid;
+    }
+    *R_out = 0.5 * (lo + hi);
+    return RHG_OK;
+}
+
+static bool make_boundaries(double R, int B, double p, double *c) {
+    if (!(R > 0.0) || !std::isfinite(R) || B < 1 || B > MAX_BANDS || !(p > 0.0) || !(p <= 1.0)) return false;
+    c[0] = 0.0;
+    if (p == 1.0) {
+        for (int i = 1; i < B; ++i) c[i] = R * i / B;
+    } else {
+        // c_i = c_1 (1 - p^i) / (1 - p) with c_1 = (1 - p) R / (1 - p^B): c_i = R (1 - p^i)/(1 - p^B)
+        const double denom = 1.0 - std::pow(p, (double)B);
+        for (int i = 1; i < B; ++i) c[i] = R * (1.0 - std::pow(p, (double)i)) / denom;
+    }
+    c[B] = R;
+    for (int i = 0; i < B; ++i)
+        if (!(c[i + 1] > c[i])) return false;
+    return true;
+}
+
+static int default_bands(uint64_t n) {
+    int b = 0;
+    while (b < 63 && (1ull << b) < n) ++b;
+    return std::max(1, std::min(b, MAX_BANDS));
+}
+
+extern "C" rhg_status rhg_band_boundaries(double R, uint32_t num_bands, double band_ratio, double *c_out) {
+    if (!c_out) return RHG_EINVAL;
+    int B = num_bands ? (int)num_bands : 0;
+    double p = band_ratio > 0.0 ? band_ratio : 0.9;
+    if (B < 1 || B > MAX_BANDS) return RHG_EINVAL;
+    return make_boundaries(R, B, p, c_out) ? RHG_OK : RHG_EINVAL;
+}
+
+extern "C" const char *rhg_status_str(rhg_status s) {
+    switch (s) {
+        case RHG_OK: return "ok";
+        case RHG_EINVAL: return "invalid argument";
+        case RHG_ENOMEM: return "out of memory";
+        case RHG_EDEVICE: return "HIP device error";
+        case RHG_ERANGE: return "size out of range";
+        case RHG_ETRUNC: return "buffer too small";
+        case RHG_EBUSY: return "not ready";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *rhg_version(void) { return "rhg-gfx950 0.1.0"; }
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+using namespace rhgi;
+
+void *Ctx::dev_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (alloc_fn) return alloc_fn(bytes, alloc_user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Ctx::dev_free(void *p) {
+    if (!p) return;
+    if (free_fn) free_fn(p, alloc_user);
+    else (void)hipFree(p);
+}
+
+void *Ctx::buf(int slot, size_t bytes) {
+    SlotBuf &s = slots[slot];
+    if (s.cap >= bytes && s.ptr) return s.ptr;
+    if (s.ptr) dev_free(s.ptr);
+    s.ptr = nullptr;
+    s.cap = 0;
+    size_t want = std::max<size_t>(bytes + bytes / 8, 4096);
+    s.ptr = dev_alloc(want);
+    if (!s.ptr) return nullptr;
+    s.cap = want;
+    return s.ptr;
+}
+
+Ctx::~Ctx() {
+    for (auto &s : slots) dev_free(s.ptr);
+    for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+    if (pinned) (void)hipHostFree(pinned);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+extern "C" rhg_status rhg_ctx_create(int device, void *hip_stream, rhg_ctx **out) {
+    if (!out) return RHG_EINVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return count == 0 ? RHG_EDEVICE : RHG_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) return RHG_EDEVICE;
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return RHG_ENOMEM;
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return RHG_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return RHG_EDEVICE;
+        }
+    if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        delete c;
+        return RHG_ENOMEM;
+    }
+    *out = reinterpret_cast<rhg_ctx *>(c);
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_ctx_set_allocator(rhg_ctx *ctx, void *(*alloc)(size_t, void *),
+                                            void (*free_fn)(void *, void *), void *user) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || (alloc && !free_fn)) return RHG_EINVAL;
+    for (auto &s : c->slots) {
+        c->dev_free(s.ptr);
+        s.ptr = nullptr;
+        s.cap = 0;
+    }
+    c->alloc_fn = alloc;
+    c->free_fn = alloc ? free_fn : nullptr;
+    c->alloc_user = alloc ? user : nullptr;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return RHG_EINVAL;
+    if (option == RHG_OPT_FP32_EXHAUSTIVE) {
+        c->exhaustive = value ? 1 : 0;
+        return RHG_OK;
+    }
+    return RHG_EINVAL;
+}
+
+extern "C" void rhg_ctx_destroy(rhg_ctx *ctx) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+// ---------------------------------------------------------------------------
+// Generation
+// ---------------------------------------------------------------------------
+namespace rhgi {
+
+static rhg_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return RHG_OK;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? RHG_ENOMEM : RHG_EDEVICE;
+}
+
+#define RHG_TRY(expr)                      \
+    do {                                   \
+        rhg_status _s = (expr);            \
+        if (_s != RHG_OK) return _s;       \
+    } while (0)
+#define RHG_HIP(expr) RHG_TRY(hip_status(expr))
+#define RHG_BUF(var, type, slot, count)                                  \
+    type *var = (type *)c->buf((slot), sizeof(type) * (size_t)(count));  \
+    if (!var) return RHG_ENOMEM
+
+static int ceil_log2(uint64_t x) {
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+// Validates and fills the generation description.
+rhg_status describe(const Request &rq, Plan &pl) {
+    if (rq.n < 2 || rq.n >= (1ull << 31)) return rq.n < 2 ? RHG_EINVAL : RHG_ERANGE;
+    if (!(rq.R > 0.0) || !std::isfinite(rq.R) || rq.R > 700.0) return RHG_EINVAL;
+    if (rq.precision != RHG_FP64 && rq.precision != RHG_FP32_RECHECK) return RHG_EINVAL;
+    if (rq.precision == RHG_FP32_RECHECK && rq.R > 43.0) return RHG_EINVAL;
+    if (rq.mode == SRC_SEED && !(rq.alpha > 0.0 && std::isfinite(rq.alpha))) return RHG_EINVAL;
+    int B = rq.num_bands ? (int)rq.num_bands : default_bands(rq.n);
+    double p = rq.band_ratio > 0.0 ? rq.band_ratio : 0.9;
+    if (B < 1 || B > MAX_BANDS) return RHG_EINVAL;
+    pl.B = B;
+    pl.p = p;
+    if (!make_boundaries(rq.R, B, p, pl.c)) return RHG_EINVAL;
+    pl.n = rq.n;
+    pl.R = rq.R;
+    pl.K = std::cosh(rq.R);
+    pl.fp32 = rq.precision == RHG_FP32_RECHECK;
+    return RHG_OK;
+}
+
+static float round_down_f32(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, 0.0f);
+    return f;
+}
+static float round_up_f32(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
+    RHG_HIP(hipSetDevice(c->device));
+    const hipStream_t st = c->stream;
+    const uint64_t n = pl.n;
+    const int B = pl.B;
+    c->generation++;
+    pl.generation = c->generation;
+
+    Source src{};
+    src.mode = rq.mode;
+    src.n = n;
+    src.seed = rq.seed;
+    src.alpha = rq.alpha;
+    src.R = rq.R;
+    src.sinh_half_aR = std::sinh(rq.alpha * rq.R / 2.0);
+    src.theta = rq.theta;
+    src.r = rq.r;
+    src.table = rq.table;
+
+    RHG_BUF(keys, uint32_t, S_KEYS, n);
+    RHG_BUF(vals, uint32_t, S_VALS, n);
+    RHG_BUF(keys2, uint32_t, S_KEYS2, n);
+    RHG_BUF(vals2, uint32_t, S_VALS2, n);
+    RHG_BUF(hist, uint32_t, S_HIST, MAX_BANDS + 8);
+    int *err = (int *)(hist + MAX_BANDS + 4);
+
+    RHG_HIP(hipEventRecord(c->ev[EV_KEYS0], st));
+    rhgk::keys(src, B, pl.c, keys, vals, hist, err, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_KEYS1], st));
+    // slab sizes -> layout
+    RHG_HIP(hipMemcpyAsync(c->pinned, hist, sizeof(uint32_t) * (MAX_BANDS + 8), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipStreamSynchronize(st));
+    const uint32_t *hh = (const uint32_t *)c->pinned;
+    if (hh[MAX_BANDS + 4] != 0) return RHG_EINVAL;  // coordinates out of range
+
+    Geo &g = pl.geo;
+    std::memset(&g, 0, sizeof(Geo));
+    g.n = (uint32_t)n;
+    g.B = B;
+    g.R = pl.R;
+    g.K = pl.K;
+    g.Kw = pl.K * (1.0 + 0x1p-30);
+    g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
+    g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
+    uint64_t acc = 0, wins = 0, btab_len = 0;
+    for (int j = 0; j < B; ++j) {
+        g.c[j] = pl.c[j];
+        g.shc[j] = std::sinh(pl.c[j]);
+        g.bs[j] = (uint32_t)acc;
+        g.winbase[j] = wins;
+        uint32_t nj = hh[j];
+        wins += (uint64_t)nj * (uint64_t)(B - j);
+        int bits = std::max(0, std::min(24, ceil_log2(nj) - 1));
+        g.bshift[j] = QBITS - bits;
+        g.bto[j] = (uint32_t)btab_len;
+        btab_len += (1ull << bits) + 1;
+        acc += nj;
+    }
+    g.c[B] = pl.c[B];
+    g.bs[B] = (uint32_t)acc;
+    g.winbase[B] = wins;
+    pl.windows = wins;
+    if (acc != n) return RHG_EDEVICE;
+
+    // sort
+    const int key_bits = QBITS + std::max(1, ceil_log2((uint64_t)B));
+    void *sort_scr = c->buf(S_SORTSCR, rhgk::sort_scratch_bytes(n));
+    if (!sort_scr) return RHG_ENOMEM;
+    RHG_HIP(hipEventRecord(c->ev[EV_SORT0], st));
+    rhgk::radix_sort(keys, vals, keys2, vals2, sort_scr, n, key_bits, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_SORT1], st));
+
+    // table in sorted order + bucket index
+    RHG_BUF(th, double, S_TH, n);
+    RHG_BUF(rr, double, S_RR, n);
+    RHG_BUF(ep, double, S_EP, n);
+    RHG_BUF(em, double, S_EM, n);
+    RHG_BUF(sh, double, S_SH, n);
+    RHG_BUF(hs, double, S_HS, n);
+    RHG_BUF(hc, double, S_HC, n);
+    float *ep32 = nullptr, *em32 = nullptr, *sh32 = nullptr;
+    if (pl.fp32) {
+        ep32 = (float *)c->buf(S_EP32, sizeof(float) * n);
+        em32 = (float *)c->buf(S_EM32, sizeof(float) * n);
+        sh32 = (float *)c->buf(S_SH32, sizeof(float) * n);
+        if (!ep32 || !em32 || !sh32) return RHG_ENOMEM;
+    }
+    rhgk::gather(src, vals, n, th, rr, ep, em, sh, hs, hc, ep32, em32, sh32, st);
+    RHG_BUF(btab, uint32_t, S_BTAB, btab_len);
+    g.keys = keys;
+    g.idx = vals;
+    g.th = th;
+    g.rr = rr;
+    g.ep = ep;
+    g.em = em;
+    g.sh = sh;
+    g.hs = hs;
+    g.hc = hc;
+    g.ep32 = ep32;
+    g.em32 = em32;
+    g.sh32 = sh32;
+    g.btab = btab;
+    rhgk::bucket_index(g, btab, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
+
+    // window plan and work units
+    const uint64_t nb = (n + BATCH - 1) / BATCH;
+    RHG_BUF(win, uint2, S_WIN, std::max<uint64_t>(wins, 1));
+    RHG_BUF(bcand, uint64_t, S_BCAND, nb);
+    RHG_BUF(boff, uint64_t, S_BOFF, nb + 1);
+    RHG_BUF(nunits, uint64_t, S_NUNITS, nb);
+    RHG_BUF(uoff, uint64_t, S_UOFF, nb + 1);
+    void *scan_scr = c->buf(S_SCANSCR, rhgk::scan_scratch_bytes(std::max<uint64_t>(nb, 1ull << 22)));
+    if (!scan_scr) return RHG_ENOMEM;
+    rhgk::plan(g, win, bcand, st);
+    rhgk::scan_u64(bcand, boff, nb, scan_scr, st);
+    rhgk::units_per_batch(bcand, nb, nunits, st);
+    rhgk::scan_u64(nunits, uoff, nb, scan_scr, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_PLAN1], st));
+    uint64_t *pin = (uint64_t *)c->pinned;
+    RHG_HIP(hipMemcpyAsync(pin + 0, boff + nb, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipMemcpyAsync(pin + 1, uoff + nb, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipStreamSynchronize(st));
+    pl.candidates = pin[0];
+    const uint64_t U = pin[1];
+    if (U >= (1ull << 31)) return RHG_ERANGE;
+    pl.n_units = U;
+
+    RHG_BUF(ubatch, uint32_t, S_UBATCH, std::max<uint64_t>(U, 1));
+    RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(U, 1));
+    RHG_BUF(ueoff, uint64_t, S_UEOFF, U + 1);
+    RHG_BUF(stats, unsigned long long, S_STATS, 4);
+    void *scan2 = c->buf(S_SCANSCR2, rhgk::scan_scratch_bytes(std::max<uint64_t>(U, 1)));
+    if (!scan2) return RHG_ENOMEM;
+    rhgk::unit_batch_fill(uoff, nb, ubatch, st);
+    RHG_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, st));
+
+    rhgk::QueryArgs &qa = pl.qa;
+    std::memset(&qa, 0, sizeof(qa));
+    qa.geo = g;
+    qa.win = win;
+    qa.batch_cand = bcand;
+    qa.unit_off = uoff;
+    qa.unit_batch = ubatch;
+    qa.n_units = U;
+    qa.unit_edges = uedges;
+    qa.unit_edge_off = ueoff;
+    qa.stats = stats;
+    qa.exhaustive = c->exhaustive;
+    RHG_HIP(hipEventRecord(c->ev[EV_COUNT0], st));
+    rhgk::query_count(qa, pl.fp32, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
+    rhgk::scan_u32(uedges, ueoff, U, scan2, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
+    RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipStreamSynchronize(st));
+    RHG_HIP(hipGetLastError());
+    pl.m = pin[2];
+    pl.rechecks = pin[3];
+    pl.disagreements = pin[4];
+    return RHG_OK;
+}
+
+rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
+    if (pl.generation != c->generation) return RHG_EINVAL;  // context reused since the count
+    RHG_HIP(hipSetDevice(c->device));
+    const hipStream_t st = c->stream;
+    pl.qa.out = out;
+    pl.qa.out_capacity = pl.m;
+    RHG_HIP(hipEventRecord(c->ev[EV_EMIT0], st));
+    rhgk::query_emit(pl.qa, pl.fp32, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_EMIT1], st));
+    RHG_HIP(hipStreamSynchronize(st));
+    RHG_HIP(hipGetLastError());
+    // phase device times: each pair of events brackets only that phase's launches
+    const int pairs[7][2] = {{EV_KEYS0, EV_KEYS1}, {EV_SORT0, EV_SORT1}, {EV_SORT1, EV_TABLE1},
+                             {EV_TABLE1, EV_PLAN1}, {EV_COUNT0, EV_COUNT1}, {EV_COUNT1, EV_SCAN1},
+                             {EV_EMIT0, EV_EMIT1}};
+    double tot = 0;
+    for (int k = 0; k < 7; ++k) {
+        float t = 0;
+        (void)hipEventElapsedTime(&t, c->ev[pairs[k][0]], c->ev[pairs[k][1]]);
+        pl.ms[k] = t;
+        tot += t;
+    }
+    pl.ms[7] = tot;
+    pl.emitted = true;
+    return RHG_OK;
+}
+
+}  // namespace rhgi
+
+// ---------------------------------------------------------------------------
+// Graph handles and ABI entry points
+// ---------------------------------------------------------------------------
+static rhg_status request_from_params(const rhg_params *p, Request &rq) {
+    if (!p) return RHG_EINVAL;
+    rq = Request{};
+    rq.mode = SRC_SEED;
+    rq.n = p->n;
+    rq.alpha = p->alpha;
+    rq.seed = p->seed;
+    rq.precision = p->precision;
+    rq.num_bands = p->num_bands;
+    rq.band_ratio = p->band_ratio;
+    if (p->R > 0.0) {
+        rq.R = p->R;
+    } else {
+        rhg_status s = rhg_target_radius(p->n, p->alpha, p->kbar, &rq.R);
+        if (s != RHG_OK) return s;
+    }
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return RHG_EINVAL;
+    return RHG_OK;
+}
+
+namespace rhgi {
+
+static void graph_release(Graph *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    auto fr = [&](void *p) {
+        if (!p) return;
+        if (g->free_fn) g->free_fn(p, g->alloc_user);
+        else (void)hipFree(p);
+    };
+    fr(g->edges);
+    fr(g->d_theta);
+    fr(g->d_r);
+    fr(g->d_table);
+    delete g;
+}
+
+static void *graph_alloc(Ctx *c, size_t bytes) { return c->dev_alloc(bytes); }
+
+// Full generation into a graph; emit=false leaves a count-only plan.
+rhg_status generate(Ctx *c, const Request &rq, bool emit, Graph **out, uint64_t *m_out) {
+    if (!c || !out) return RHG_EINVAL;
+    Graph *g = new (std::nothrow) Graph();
+    if (!g) return RHG_ENOMEM;
+    g->device = c->device;
+    g->ctx = c;
+    g->free_fn = c->free_fn;
+    g->alloc_user = c->alloc_user;
+    g->rq = rq;
+    rhg_status s = describe(rq, g->pl);
+    if (s != RHG_OK) {
+        delete g;
+        return s;
+    }
+    (void)hipSetDevice(c->device);
+    // keep caller coordinates for the coordinate forms (copy_points / emit)
+    if (rq.mode != SRC_SEED) {
+        const size_t nb = sizeof(double) * rq.n;
+        g->d_theta = (double *)graph_alloc(c, nb);
+        g->d_r = (double *)graph_alloc(c, nb);
+        if (rq.mode == SRC_TABLE) g->d_table = (double *)graph_alloc(c, 5 * nb);
+        if (!g->d_theta || !g->d_r || (rq.mode == SRC_TABLE && !g->d_table)) {
+            graph_release(g);
+            return RHG_ENOMEM;
+        }
+        hipMemcpyKind k = rq.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        s = hip_status(hipMemcpyAsync(g->d_theta, rq.theta, nb, k, c->stream));
+        if (s == RHG_OK) s = hip_status(hipMemcpyAsync(g->d_r, rq.r, nb, k, c->stream));
+        if (s == RHG_OK && rq.mode == SRC_TABLE)
+            s = hip_status(hipMemcpyAsync(g->d_table, rq.table, 5 * nb, k, c->stream));
+        if (s != RHG_OK) {
+            graph_release(g);
+            return s;
+        }
+        g->rq.theta = g->d_theta;
+        g->rq.r = g->d_r;
+        g->rq.table = g->d_table;
+        g->rq.on_device = 1;
+    }
+    s = run_count(c, g->rq, g->pl);
+    if (s == RHG_OK && emit) {
+        const uint64_t m = g->pl.m;
+        g->edges = (int32_t *)graph_alloc(c, std::max<uint64_t>(m, 1) * 2 * sizeof(int32_t));
+        if (!g->edges) s = RHG_ENOMEM;
+        if (s == RHG_OK) s = run_emit(c, g->pl, (int2 *)g->edges);
+    }
+    if (s != RHG_OK) {
+        graph_release(g);
+        return s;
+    }
+    if (m_out) *m_out = g->pl.m;
+    *out = g;
+    return RHG_OK;
+}
+
+}  // namespace rhgi
+
+extern "C" rhg_status rhg_generate(rhg_ctx *ctx, const rhg_params *params, rhg_graph **out) {
+    Request rq;
+    rhg_status s = request_from_params(params, rq);
+    if (s != RHG_OK) return s;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+static rhg_status coords_request(uint64_t n, const double *theta, const double *r, const double *table, double R,
+                                 rhg_precision precision, int on_device, Request &rq) {
+    if (!theta || !r) return RHG_EINVAL;
+    rq = Request{};
+    rq.mode = table ? SRC_TABLE : SRC_COORDS;
+    rq.n = n;
+    rq.alpha = 1.0;
+    rq.R = R;
+    rq.precision = precision;
+    rq.theta = theta;
+    rq.r = r;
+    rq.table = table;
+    rq.on_device = on_device ? 1 : 0;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_generate_from_coords(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
+                                               double R, rhg_precision precision, int coords_on_device,
+                                               rhg_graph **out) {
+    Request rq;
+    rhg_status s = coords_request(n, theta, r, nullptr, R, precision, coords_on_device, rq);
+    if (s != RHG_OK || !out) return s != RHG_OK ? s : RHG_EINVAL;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
+                                              const double *table5xn, double R, rhg_precision precision,
+                                              int on_device, rhg_graph **out) {
+    if (!table5xn) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = coords_request(n, theta, r, table5xn, R, precision, on_device, rq);
+    if (s != RHG_OK || !out) return s != RHG_OK ? s : RHG_EINVAL;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_graph **plan, uint64_t *m) {
+    if (!plan || !m) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = request_from_params(params, rq);
+    if (s != RHG_OK) return s;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, false, &g, m);
+    if (s == RHG_OK) *plan = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_emit(rhg_ctx *ctx, rhg_graph *plan, int32_t *dev_pairs, uint64_t capacity_pairs) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    Graph *g = reinterpret_cast<Graph *>(plan);
+    if (!c || !g || g->ctx != c || g->pl.emitted) return RHG_EINVAL;
+    if (capacity_pairs < g->pl.m) return RHG_ETRUNC;
+    if (!dev_pairs && g->pl.m) return RHG_EINVAL;
+    return run_emit(c, g->pl, (int2 *)dev_pairs);
+}
+
+extern "C" rhg_status rhg_graph_num_edges(const rhg_graph *gr, uint64_t *m) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !m) return RHG_EINVAL;
+    *m = g->pl.m;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_graph_num_points(const rhg_graph *gr, uint64_t *n) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !n) return RHG_EINVAL;
+    *n = g->pl.n;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_graph_radius(const rhg_graph *gr, double *R) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !R) return RHG_EINVAL;
+    *R = g->pl.R;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_graph_edges_device(const rhg_graph *gr, const int32_t **pairs) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !pairs || !g->edges) return RHG_EINVAL;
+    *pairs = g->edges;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_graph_copy_edges(const rhg_graph *gr, int32_t *host_pairs, uint64_t capacity_pairs) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !g->edges) return RHG_EINVAL;
+    if (capacity_pairs < g->pl.m) return RHG_ETRUNC;
+    if (!g->pl.m) return RHG_OK;
+    if (!host_pairs) return RHG_EINVAL;
+    (void)hipSetDevice(g->device);
+    return hip_status(hipMemcpy(host_pairs, g->edges, g->pl.m * 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+}
+
+extern "C" rhg_status rhg_graph_copy_points(const rhg_graph *gr, double *theta, double *r, double *table5xn,
+                                           double *K) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g) return RHG_EINVAL;
+    if (K) *K = g->pl.K;
+    if (!theta && !r && !table5xn) return RHG_OK;
+    (void)hipSetDevice(g->device);
+    const uint64_t n = g->pl.n;
+    Source src{};
+    src.mode = g->rq.mode;
+    src.n = n;
+    src.seed = g->rq.seed;
+    src.alpha = g->rq.alpha;
+    src.R = g->rq.R;
+    src.sinh_half_aR = std::sinh(g->rq.alpha * g->rq.R / 2.0);
+    src.theta = g->d_theta;
+    src.r = g->d_r;
+    src.table = g->d_table;
+    double *d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * 7 * n) != hipSuccess) {
+        (void)hipGetLastError();
+        return RHG_ENOMEM;
+    }
+    rhgk::point_values(src, n, d, d + n, d + 2 * n, nullptr);
+    rhg_status s = hip_status(hipDeviceSynchronize());
+    if (s == RHG_OK && theta) s = hip_status(hipMemcpy(theta, d, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (s == RHG_OK && r) s = hip_status(hipMemcpy(r, d + n, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (s == RHG_OK && table5xn)
+        s = hip_status(hipMemcpy(table5xn, d + 2 * n, sizeof(double) * 5 * n, hipMemcpyDeviceToHost));
+    (void)hipFree(d);
+    return s;
+}
+
+extern "C" rhg_status rhg_graph_stats(const rhg_graph *gr, rhg_stats *st) {
+    const Graph *g = reinterpret_cast<const Graph *>(gr);
+    if (!g || !st) return RHG_EINVAL;
+    std::memset(st, 0, sizeof(*st));
+    st->edges = g->pl.m;
+    st->candidates = g->pl.candidates;
+    st->rechecks = g->pl.rechecks;
+    st->windows = g->pl.windows;
+    st->disagreements = g->pl.disagreements;
+    for (int k = 0; k < 8; ++k) st->ms[k] = g->pl.ms[k];
+    st->bytes_moved = algorithmic_bytes(g->pl);
+    return RHG_OK;
+}
+
+extern "C" void rhg_graph_free(rhg_graph *gr) { graph_release(reinterpret_cast<Graph *>(gr)); }

@@ -1,0 +1,95 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/rhg.h declares, and its host-only calls (parameters, boundaries,
+argument validation) behave -- no GPU needed, no kernel launched."""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1606_09481_amd import rhg
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import os
+    if not os.path.exists(rhg.LIB_PATH):
+        from paper_1606_09481_amd import build
+        build.build()
+    return rhg.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = rhg.header_functions()
+    assert len(names) >= 25
+    out = subprocess.run(["nm", "-D", "--defined-only", rhg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [x for x in names if x not in exported]
+    assert not missing, missing
+    for x in names:
+        assert hasattr(lib, x)
+
+
+@pytest.mark.parametrize("n,alpha,kbar", [(1e4, 1.0, 10), (1e6, 1.0, 20), (1e7, 0.75, 100), (4e6, 0.55, 64),
+                                          (4e6, 1.0, 64), (4e6, 1.5, 64)])
+def test_target_radius_agrees_with_oracle(lib, orc, n, alpha, kbar):
+    R = rhg.rhg_target_radius(int(n), alpha, kbar)
+    Ro = orc.target_radius(n, alpha, kbar)
+    assert abs(R - Ro) <= 1e-13 * Ro
+
+
+@pytest.mark.parametrize("args", [(10000, 0.5, 10.0), (10000, 1.0, 0.0), (10000, 1.0, 1e15), (1, 1.0, 1.0),
+                                  (10000, float("nan"), 10.0)])
+def test_target_radius_rejects(lib, args):
+    with pytest.raises(rhg.RhgError) as e:
+        rhg.rhg_target_radius(*args)
+    assert e.value.status == rhg.RHG_EINVAL
+
+
+@pytest.mark.parametrize("R,B,p", [(26.5, 24, 0.9), (15.68, 14, 0.9), (10.0, 1, 0.9), (30.0, 32, 0.5)])
+def test_band_boundaries(lib, orc, R, B, p):
+    c = rhg.rhg_band_boundaries(R, B, p)
+    assert c[0] == 0.0 and c[-1] == R and np.all(np.diff(c) > 0)
+    assert np.allclose(c, orc.boundaries(R, B, p), rtol=1e-13, atol=1e-13)
+    ce = rhg.rhg_band_boundaries(R, B, 1.0)
+    assert np.allclose(np.diff(ce), R / B)
+
+
+def test_band_boundaries_rejects(lib):
+    for args in [(10.0, 0, 0.9), (10.0, 33, 0.9), (-1.0, 4, 0.9), (10.0, 4, 1.5)]:
+        with pytest.raises(rhg.RhgError):
+            rhg.rhg_band_boundaries(*args)
+
+
+def test_status_strings_and_version(lib):
+    assert rhg.status_str(0) == "ok"
+    assert "invalid" in rhg.status_str(-1)
+    assert rhg.status_str(-99) == "unknown status"
+    assert rhg.rhg_version().startswith("rhg-gfx950")
+
+
+def test_null_handles_rejected(lib):
+    m = ctypes.c_uint64()
+    assert lib.rhg_graph_num_edges(None, ctypes.byref(m)) == rhg.RHG_EINVAL
+    p = rhg.params(1000)
+    g = ctypes.c_void_p()
+    assert lib.rhg_generate(None, ctypes.byref(p), ctypes.byref(g)) == rhg.RHG_EINVAL
+    assert lib.rhg_emit(None, None, None, 0) == rhg.RHG_EINVAL
+    assert lib.rhg_graph_stats(None, None) == rhg.RHG_EINVAL
+    lib.rhg_graph_free(None)
+    lib.rhg_ctx_destroy(None)
+
+
+def test_product_has_no_oracle_dependency():
+    # the product package must not import, link or load anything from oracle/
+    import os
+    import re
+    root = os.path.dirname(rhg.HERE)
+    for dirpath, _, files in os.walk(rhg.HERE):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b|rhg_oracle|liboracle|orc_", txt), f
+    out = subprocess.run(["ldd", rhg.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out
+    assert root

@@ -1,0 +1,253 @@
+"""GPU parity of the HIP path (through the C ABI) against the oracle.
+
+* Same table bits on both sides (rhg_generate_from_table): the edge set must be
+  identical, bit for bit, for model, uniform and adversarial points, every
+  slab count and ratio, both precision forms.
+* Seeded generation (rhg_generate): the device samples and builds its own
+  table; angles must equal the oracle's bit for bit, radii and table entries
+  within 2 ulp, and the edge sets agree except pairs within that rounding of
+  the threshold (reported, at most a handful).
+* FP32 filter + FP64 recheck gives byte-identical output to FP64.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import inputs
+import parity
+from paper_1606_09481_amd import rhg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    rhg.load()
+    c = rhg.rhg_ctx_create(0)
+    yield c
+    rhg.rhg_ctx_destroy(c)
+
+
+def _edges(g):
+    e = rhg.rhg_graph_copy_edges(g)
+    rhg.rhg_graph_free(g)
+    return e
+
+
+def _from_table(ctx, orc, th, r, R, prec=rhg.RHG_FP64):
+    t = orc.table(th, r)
+    g = rhg.rhg_generate_from_table(ctx, th, r, t, R, prec)
+    st = rhg.rhg_graph_stats(g)
+    return _edges(g), t, st
+
+
+def _ulps(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.spacing(np.maximum(np.abs(a), np.abs(b)))
+
+
+# ---------------------------------------------------------------- identical table bits
+@pytest.mark.parametrize("n,alpha,kbar,seed", [(10_000, 1.0, 10, 1), (20_000, 0.55, 8, 2), (15_000, 1.5, 30, 3),
+                                               (12_345, 0.75, 60, 4)])
+def test_table_mode_exact_model(ctx, orc, n, alpha, kbar, seed):
+    print("case", n, alpha, kbar, seed, flush=True)
+    R = orc.target_radius(n, alpha, kbar)
+    th, r = orc.sample(n, alpha, R, seed)
+    e, t, st = _from_table(ctx, orc, th, r, R)
+    ref = orc.brute(t, math.cosh(R))
+    parity.assert_valid(e, n)
+    parity.assert_same(e, ref)
+    assert st["edges"] == len(ref) and st["candidates"] >= len(ref)
+    e32, _, st32 = _from_table(ctx, orc, th, r, R, rhg.RHG_FP32_RECHECK)
+    assert np.array_equal(e32, e), "FP32+recheck output differs from FP64 output"
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_table_mode_exact_adversarial(ctx, orc, seed):
+    n, R = 9_000, 14.0
+    c = orc.boundaries(R, orc.default_bands(n), 0.9)
+    th, r = inputs.adversarial_coords(n, R, c, seed)
+    print("adversarial seed", seed, flush=True)
+    e, t, _ = _from_table(ctx, orc, th, r, R)
+    parity.assert_valid(e, n)
+    parity.assert_same(e, orc.brute(t, math.cosh(R)))
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_table_mode_exact_uniform_radii(ctx, orc, seed):
+    n, R = 6_000, 12.0
+    th, r = inputs.uniform_coords(n, R, seed)
+    e, t, _ = _from_table(ctx, orc, th, r, R)
+    parity.assert_same(e, orc.brute(t, math.cosh(R)))
+
+
+def test_table_mode_near_threshold(ctx, orc):
+    from test_oracle_sweep import _threshold_pairs, _window_edge_pairs
+    for R, seed in [(14.0, 0), (22.0, 1), (27.0, 2)]:
+        th1, r1 = _threshold_pairs(R, 60, seed)
+        th2, r2, _ = _window_edge_pairs(orc, R, 80, seed + 10)
+        th3, r3 = inputs.outer_heavy_coords(3000, R, seed + 7)
+        th = np.concatenate([th1, th2, th3])
+        r = np.concatenate([r1, r2, r3])
+        e, t, _ = _from_table(ctx, orc, th, r, R)
+        parity.assert_same(e, orc.brute(t, math.cosh(R)))
+        e32, _, st = _from_table(ctx, orc, th, r, R, rhg.RHG_FP32_RECHECK)
+        assert np.array_equal(e32, e)
+        assert st["rechecks"] > 0     # the constructed pairs fall inside the FP32 margin
+
+
+def test_table_mode_degenerate(ctx, orc):
+    cases = [
+        (np.array([0.1, 0.2]), np.array([3.0, 3.0]), 5.0),
+        (np.array([0.0, 2 * np.pi]), np.array([9.0, 9.0]), 9.0),
+        (np.full(300, 1.0), np.full(300, 7.0), 7.0),            # all points equal: complete graph
+        (np.linspace(0, 6, 200), np.zeros(200), 9.0),           # all at the origin
+        (np.full(257, 2 * np.pi), np.full(257, 9.0), 9.0),
+        (np.array([3.0, 3.0 + np.pi]), np.array([4.0, 4.0]), 7.9),  # opposite, distance 8 > R
+    ]
+    for th, r, R in cases:
+        e, t, _ = _from_table(ctx, orc, th, r, R)
+        parity.assert_same(e, orc.brute(t, math.cosh(R)))
+
+
+@pytest.mark.parametrize("B,p", [(1, 0.9), (2, 0.9), (5, 0.5), (32, 0.9), (20, 1.0), (0, 0.99)])
+def test_slab_choice_does_not_change_edges(ctx, orc, B, p):
+    n, alpha, kbar = 20_000, 0.75, 20
+    R = orc.target_radius(n, alpha, kbar)
+    base = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=5))
+    e0 = _edges(base)
+    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=5, num_bands=B, band_ratio=p))
+    parity.assert_same(_edges(g), e0)
+
+
+# ---------------------------------------------------------------- seeded generation
+@pytest.mark.parametrize("n,alpha,kbar,seed", [(10_000, 1.0, 10, 1), (50_000, 0.55, 6, 7), (30_001, 1.5, 20, 9)])
+def test_seeded_points_match_oracle_sampler(ctx, orc, n, alpha, kbar, seed):
+    R = orc.target_radius(n, alpha, kbar)
+    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=seed))
+    th, r, t, K = rhg.rhg_graph_copy_points(g)
+    rhg.rhg_graph_free(g)
+    tho, ro = orc.sample(n, alpha, R, seed)
+    assert np.array_equal(th, tho)                     # one rounding, identical on both sides
+    assert _ulps(r, ro).max() <= 4                     # device asinh vs host asinh
+    same = r == ro                                     # compare tables where the radii agree bitwise
+    assert same.mean() > 0.5
+    to = orc.table(tho, ro)
+    assert _ulps(t[:, same], to[:, same]).max() <= 2
+    assert _ulps(t[3:], to[3:]).max() <= 2             # angle entries: same angles everywhere
+    assert K == math.cosh(R)
+
+
+def test_config1_seeded_vs_bruteforce(ctx, orc):
+    """n = 10^4, alpha = 1, kbar = 10, seed 1: the device's sampled graph vs the all-pairs oracle."""
+    n, alpha, kbar = 10_000, 1.0, 10
+    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, kbar=kbar, seed=1))
+    R = rhg.rhg_graph_radius(g)
+    assert abs(R - orc.target_radius(n, alpha, kbar)) <= 1e-13 * R
+    e = _edges(g)
+    th, r = orc.sample(n, alpha, R, 1)
+    t = orc.table(th, r)
+    ref = orc.brute(t, math.cosh(R))
+    parity.assert_valid(e, n)
+    parity.assert_same_up_to_rounding(e, ref, t, math.cosh(R))
+
+
+def test_golden_fixture(ctx):
+    path = os.path.join(os.path.dirname(__file__), "golden", "n2000_a1_k10_seed1.txt")
+    with open(path) as f:
+        f.readline()
+        R = float.fromhex(f.readline().split()[1].split("=")[1])
+        stored = np.loadtxt(f, dtype=np.int32).reshape(-1, 2)
+    g = rhg.rhg_generate(ctx, rhg.params(2000, 1.0, R=R, seed=1))
+    e = _edges(g)
+    assert len(parity.np.setxor1d(parity.canonical(e), parity.canonical(stored))) <= 2
+
+
+@pytest.mark.parametrize("prec", [rhg.RHG_FP64, rhg.RHG_FP32_RECHECK])
+def test_config2_vs_band_oracle(ctx, orc, prec):
+    """n = 10^6, alpha = 1, kbar = 20 (about 10^7 edges) against the CPU band sweep."""
+    n, alpha, kbar = 1_000_000, 1.0, 20
+    R = orc.target_radius(n, alpha, kbar)
+    th, r = orc.sample(n, alpha, R, 1)
+    t = orc.table(th, r)
+    K = math.cosh(R)
+    ref = orc.band_sweep(th, r, t, R, K)
+    g = rhg.rhg_generate_from_table(ctx, th, r, t, R, prec)
+    e = _edges(g)
+    parity.assert_valid(e, n)
+    parity.assert_same(e, ref)
+    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=1, precision=prec))
+    st = rhg.rhg_graph_stats(g)
+    e2 = _edges(g)
+    parity.assert_same_up_to_rounding(e2, ref, t, K)
+    if prec == rhg.RHG_FP32_RECHECK:
+        print("config2 rechecks", st["rechecks"], "of", st["candidates"], flush=True)
+
+
+def test_fp32_exhaustive_no_disagreement(ctx, orc):
+    n, alpha, kbar = 300_000, 0.55, 12
+    c = rhg.rhg_ctx_create(0)
+    try:
+        rhg.rhg_ctx_set_option(c, rhg.RHG_OPT_FP32_EXHAUSTIVE, 1)
+        g = rhg.rhg_generate(c, rhg.params(n, alpha, kbar=kbar, seed=3, precision=rhg.RHG_FP32_RECHECK))
+        st = rhg.rhg_graph_stats(g)
+        e32 = _edges(g)
+        g = rhg.rhg_generate(c, rhg.params(n, alpha, kbar=kbar, seed=3, precision=rhg.RHG_FP64))
+        e64 = _edges(g)
+    finally:
+        rhg.rhg_ctx_destroy(c)
+    assert st["disagreements"] == 0
+    assert np.array_equal(e32, e64)
+
+
+def test_deterministic_bytes(ctx):
+    p = rhg.params(200_000, 0.75, kbar=30, seed=11)
+    a = _edges(rhg.rhg_generate(ctx, p))
+    b = _edges(rhg.rhg_generate(ctx, p))
+    assert np.array_equal(a, b)
+
+
+def test_count_emit_into_torch(ctx):
+    import torch
+    p = rhg.params(100_000, 1.0, kbar=16, seed=4)
+    plan, m = rhg.rhg_count(ctx, p)
+    out = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_emit(ctx, plan, out, m - 1)        # too small: RHG_ETRUNC, nothing written
+    rhg.rhg_emit(ctx, plan, out, m)
+    got = out.view(-1, 2).cpu().numpy()
+    rhg.rhg_graph_free(plan)
+    ref = _edges(rhg.rhg_generate(ctx, p))
+    assert np.array_equal(got, ref)
+
+
+def test_invalid_inputs(ctx):
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_generate(ctx, rhg.params(1, 1.0, kbar=2))
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_generate(ctx, rhg.params(1000, 1.0, R=50.0, precision=rhg.RHG_FP32_RECHECK))
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_generate_from_coords(ctx, np.array([0.1, 7.0]), np.array([1.0, 1.0]), 5.0)  # angle > 2pi
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_generate_from_coords(ctx, np.array([0.1, 1.0]), np.array([1.0, 6.0]), 5.0)  # r > R
+    with pytest.raises(rhg.RhgError):
+        rhg.rhg_generate_from_coords(ctx, np.array([0.1, np.nan]), np.array([1.0, 1.0]), 5.0)
+    # the context still works afterwards
+    e = _edges(rhg.rhg_generate(ctx, rhg.params(5000, 1.0, kbar=10, seed=1)))
+    assert len(e) > 0
+
+
+def test_coords_on_device(ctx, orc):
+    import torch
+    n, R = 40_000, 18.0
+    th, r = orc.sample(n, 0.8, R, 21)
+    a = _edges(rhg.rhg_generate_from_coords(ctx, th, r, R))
+    dth = torch.from_numpy(th).cuda()
+    dr = torch.from_numpy(r).cuda()
+    b = _edges(rhg.rhg_generate_from_coords(ctx, dth, dr, R))
+    assert np.array_equal(a, b)
+    t = orc.table(th, r)
+    parity.assert_same_up_to_rounding(a, orc.band_sweep(th, r, t, R, math.cosh(R)), t, math.cosh(R))
