@@ -88,9 +88,11 @@ typedef struct rhg_server rhg_server;
  *   candidates  distance tests performed (window sizes summed)
  *   rechecks    pairs the FP32 filter left undecided (FP32_RECHECK only)
  *   windows     (query, slab) windows planned
- *   ms[8]       device time per phase from HIP events on the context stream:
- *               0 sample+band keys, 1 sort, 2 table+slab index, 3 window plan,
- *               4 count, 5 scans, 6 emit, 7 total (first to last event)
+ *   ms[8]       device time per phase from HIP events on the context stream,
+ *               each pair of events bracketing only that phase's launches:
+ *               0 sample + slab keys, 1 sort + slab starts, 2 table gather,
+ *               3 slab index + window plan + unit scans, 4 count, 5 edge scan,
+ *               6 emit, 7 sum of 0-6 (host synchronisation gaps excluded)
  *   bytes_moved algorithmic HBM bytes of phases 1-6 (reads + writes the
  *               method needs), for roofline reporting */
 typedef struct {

@@ -18,37 +18,47 @@ struct BandsArg {
     double c[MAX_BANDS + 1];
 };
 
-__global__ __launch_bounds__(256) void k_keys(Source src, BandsArg bands, uint32_t *keys, uint32_t *vals,
-                                              uint32_t *hist, int *err) {
-    __shared__ uint32_t h[MAX_BANDS];
-    if (threadIdx.x < MAX_BANDS) h[threadIdx.x] = 0;
-    __syncthreads();
+__global__ __launch_bounds__(256) void k_keys(Source src, BandsArg bands, uint32_t *keys, uint32_t *vals, int *err) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < src.n) {
-        double th, r;
-        load_point(src, i, th, r);
-        if (src.mode != SRC_SEED) {
-            if (!(th >= 0.0 && th <= TWO_PI && r >= 0.0 && r <= src.R)) atomicOr(err, 1);
-        }
-        int b = 0;
-        while (b + 1 < bands.B && bands.c[b + 1] <= r) ++b;
-        keys[i] = ((uint32_t)b << QBITS) | qang(th);
-        vals[i] = (uint32_t)i;
-        atomicAdd(&h[b], 1u);
+    if (i >= src.n) return;
+    double th, r;
+    load_point(src, i, th, r);
+    if (src.mode != SRC_SEED) {
+        if (!(th >= 0.0 && th <= TWO_PI && r >= 0.0 && r <= src.R)) atomicOr(err, 1);
     }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)bands.B && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    int b = 0;
+    while (b + 1 < bands.B && bands.c[b + 1] <= r) ++b;
+    keys[i] = ((uint32_t)b << QBITS) | qang(th);
+    vals[i] = (uint32_t)i;
 }
 
-void keys(const Source &src, int B, const double *c_host, uint32_t *k, uint32_t *v, uint32_t *hist, int *err,
-          hipStream_t st) {
+void keys(const Source &src, int B, const double *c_host, uint32_t *k, uint32_t *v, int *err, hipStream_t st) {
     BandsArg ba;
     ba.B = B;
     for (int j = 0; j <= B; ++j) ba.c[j] = c_host[j];
-    hipMemsetAsync(hist, 0, sizeof(uint32_t) * B, st);
     hipMemsetAsync(err, 0, sizeof(int), st);
     uint64_t blocks = (src.n + 255) / 256;
-    if (blocks) hipLaunchKernelGGL(k_keys, dim3((unsigned)blocks), dim3(256), 0, st, src, ba, k, v, hist, err);
+    if (blocks) hipLaunchKernelGGL(k_keys, dim3((unsigned)blocks), dim3(256), 0, st, src, ba, k, v, err);
+}
+
+// Slab starts in the sorted keys: bs[j] = first position with slab >= j.
+__global__ void k_band_starts(const uint32_t *keys, uint32_t n, int B, uint32_t *bs) {
+    int j = threadIdx.x;
+    if (j > B) return;
+    uint32_t lo = 0, hi = n, x = (uint32_t)j << QBITS;
+    if (j == B) {
+        bs[j] = n;
+        return;
+    }
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    bs[j] = lo;
+}
+
+void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStream_t st) {
+    hipLaunchKernelGGL(k_band_starts, dim3(1), dim3(64), 0, st, keys, (uint32_t)n, B, bs);
 }
 
 // ---------------------------------------------------------------------------

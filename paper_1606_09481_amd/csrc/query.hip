@@ -24,8 +24,11 @@
 // cut into units of <= 4096 candidates; one wavefront runs one unit, lane k
 // taking flattened candidate t0 + k (a load-balanced search over the 64
 // window counts of the current slab), so hub queries with million-candidate
-// windows spread over many wavefronts.  Count and emit walk units
-// identically, so edge order is deterministic.
+// windows spread over many wavefronts.  The count pass evaluates the distance
+// test once per candidate and keeps the decisions as a 4096-bit map per unit;
+// the emit pass walks the unit identically, reads the map instead of
+// re-testing, and writes the pairs compacted per 64-candidate round, so the
+// edge order is deterministic.
 #include "rhg_kernels.h"
 
 namespace rhgk {
@@ -185,82 +188,115 @@ __device__ __forceinline__ int edge_test(const Geo &g, const Qv &q, uint32_t p, 
     }
 }
 
-template <int EMIT, int FP32>
-__global__ __launch_bounds__(256) void k_query(QueryArgs A) {
+// Per-unit setup shared by the count and emit passes.
+struct UnitSetup {
+    uint32_t b;
+    uint64_t r0, r1;
+    uint32_t v;
+    bool valid;
+    int iv, jmin;
+    const uint2 *mywin;
+};
+
+__device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
+    const Geo &g = A.geo;
+    UnitSetup u;
+    u.b = A.unit_batch[unit];
+    const uint64_t chunk = unit - A.unit_off[u.b];
+    u.r0 = chunk * UNIT;
+    const uint64_t bc = A.batch_cand[u.b];
+    u.r1 = (u.r0 + UNIT < bc) ? u.r0 + UNIT : bc;
+    u.v = u.b * BATCH + lane;
+    u.valid = u.v < g.n;
+    u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
+    u.jmin = (int)(g.keys[u.b * BATCH] >> QBITS);
+    u.mywin = u.valid ? A.win + win_offset(g, u.v, u.iv) : nullptr;
+    return u;
+}
+
+// Lane's window in slab j (0 count if none), scanned over the wavefront.
+__device__ __forceinline__ void slab_windows(const UnitSetup &u, int j, uint32_t &st, uint32_t &cnt,
+                                             uint32_t &excl, uint32_t &tot) {
+    st = 0;
+    cnt = 0;
+    if (u.valid && j >= u.iv) {
+        const uint2 x = u.mywin[j - u.iv];
+        st = x.x;
+        cnt = x.y;
+    }
+    const uint32_t incl = wave_incl_scan_u32(cnt);
+    tot = wave_bcast_u32(incl, 63);
+    excl = incl - cnt;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Window index of flattened candidate t: the last lane whose exclusive offset is <= t.
+__device__ __forceinline__ int find_window(const uint32_t *excl, uint32_t t) {
+    int l = 0;
+#pragma unroll
+    for (int stp = 32; stp; stp >>= 1)
+        if (excl[l + stp] <= t) l += stp;
+    return l;
+}
+
+// Count pass: decide every candidate of the unit, record the decisions as a
+// bitmap over the unit's flattened positions (64 x 64 bits), count edges.
+template <int FP32>
+__global__ __launch_bounds__(256) void k_count(QueryArgs A) {
     __shared__ uint32_t s_excl[4][64];
     __shared__ uint32_t s_start[4][64];
     __shared__ double s_qd[4][5][64];
     __shared__ float s_qf[4][3][64];
-    __shared__ uint32_t s_qi[4][64];
+    __shared__ unsigned long long s_bits[4][65];
 
     const Geo &g = A.geo;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t unit = (uint64_t)blockIdx.x * 4 + w;
     if (unit >= A.n_units) return;  // uniform per wavefront; no block-wide barriers below
-
-    const uint32_t b = A.unit_batch[unit];
-    const uint64_t chunk = unit - A.unit_off[b];
-    const uint64_t r0 = chunk * UNIT;
-    const uint64_t bc = A.batch_cand[b];
-    const uint64_t r1 = (r0 + UNIT < bc) ? r0 + UNIT : bc;
-
-    const uint32_t v = b * BATCH + lane;
-    const bool valid = v < g.n;
-    const int iv = valid ? (int)(g.keys[v] >> QBITS) : g.B;
-    const int jmin = (int)(g.keys[b * BATCH] >> QBITS);
-    if (valid) {
-        const double ep = g.ep[v], em = g.em[v], sh = g.sh[v];
-        s_qd[w][0][lane] = 0.5 * ep;
-        s_qd[w][1][lane] = 0.5 * em;
-        s_qd[w][2][lane] = 2.0 * sh;
-        s_qd[w][3][lane] = g.hs[v];
-        s_qd[w][4][lane] = g.hc[v];
+    const UnitSetup u = unit_setup(A, unit, lane);
+    if (u.valid) {
+        s_qd[w][0][lane] = 0.5 * g.ep[u.v];
+        s_qd[w][1][lane] = 0.5 * g.em[u.v];
+        s_qd[w][2][lane] = 2.0 * g.sh[u.v];
+        s_qd[w][3][lane] = g.hs[u.v];
+        s_qd[w][4][lane] = g.hc[u.v];
         if (FP32) {
-            s_qf[w][0][lane] = 0.5f * g.ep32[v];
-            s_qf[w][1][lane] = 0.5f * g.em32[v];
-            s_qf[w][2][lane] = 2.0f * g.sh32[v];
+            s_qf[w][0][lane] = 0.5f * g.ep32[u.v];
+            s_qf[w][1][lane] = 0.5f * g.em32[u.v];
+            s_qf[w][2][lane] = 2.0f * g.sh32[u.v];
         }
-        s_qi[w][lane] = g.idx[v];
     }
-    const uint2 *mywin = valid ? A.win + win_offset(g, v, iv) : nullptr;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    s_bits[w][lane] = 0ull;
+    if (lane == 0) s_bits[w][64] = 0ull;
 
     uint64_t pos = 0;  // flattened offset of slab j's segment within the batch
     uint32_t found = 0, rechecks = 0, disagree = 0;
-    uint64_t out_at = EMIT ? A.unit_edge_off[unit] : 0;
-
-    for (int j = jmin; j < g.B; ++j) {
-        uint32_t st = 0, cnt = 0;
-        if (valid && j >= iv) {
-            const uint2 x = mywin[j - iv];
-            st = x.x;
-            cnt = x.y;
-        }
-        const uint32_t incl = wave_incl_scan_u32(cnt);
-        const uint32_t tot = wave_bcast_u32(incl, 63);
-        if (pos + tot <= r0) {
+    for (int j = u.jmin; j < g.B; ++j) {
+        uint32_t st, cnt, excl, tot;
+        slab_windows(u, j, st, cnt, excl, tot);
+        if (pos + tot <= u.r0) {
             pos += tot;
             continue;
         }
-        if (pos >= r1) break;
-        s_excl[w][lane] = incl - cnt;
+        if (pos >= u.r1) break;
+        wave_lds_sync();
+        s_excl[w][lane] = excl;
         s_start[w][lane] = st;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t a = (r0 > pos) ? (uint32_t)(r0 - pos) : 0u;
-        const uint32_t e = (r1 - pos < tot) ? (uint32_t)(r1 - pos) : tot;
+        wave_lds_sync();
+        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
+        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
         const uint32_t be = g.bs[j + 1], nj = be - g.bs[j];
         for (uint32_t t0 = a; t0 < e; t0 += 64) {
             const uint32_t t = t0 + lane;
             int flag = 0;
-            uint32_t p = 0;
-            int l = 0;
             if (t < e) {
-#pragma unroll
-                for (int stp = 32; stp; stp >>= 1)
-                    if (s_excl[w][l + stp] <= t) l += stp;
-                p = s_start[w][l] + (t - s_excl[w][l]);
+                const int l = find_window(s_excl[w], t);
+                uint32_t p = s_start[w][l] + (t - s_excl[w][l]);
                 if (p >= be) p -= nj;
                 if (p >= be) p = be - 1;  // unreachable for consistent windows; keeps reads in bounds
                 Qv q;
@@ -274,32 +310,91 @@ __global__ __launch_bounds__(256) void k_query(QueryArgs A) {
                     q.hem32 = s_qf[w][1][l];
                     q.sh2_32 = s_qf[w][2][l];
                 }
-                flag = edge_test<FP32>(g, q, p, rechecks, disagree, EMIT ? 0 : A.exhaustive);
+                flag = edge_test<FP32>(g, q, p, rechecks, disagree, A.exhaustive);
             }
-            if (!EMIT) {
-                found += (uint32_t)flag;
-            } else {
-                const uint64_t m = __ballot(flag);
-                if (flag) {
-                    const uint32_t qi = s_qi[w][l], wi = g.idx[p];
-                    const uint32_t lo = qi < wi ? qi : wi, hi = qi < wi ? wi : qi;
-                    const uint64_t at = out_at + (uint64_t)__popcll(m & lt);
-                    if (at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
+            const uint64_t m = __ballot(flag);
+            if (m) {
+                found += (uint32_t)__popcll(m);
+                if (lane == 0) {
+                    const uint32_t o = (uint32_t)(pos + t0 - u.r0);
+                    const uint32_t wd = o >> 6, sh = o & 63u;
+                    s_bits[w][wd] |= m << sh;
+                    if (sh) s_bits[w][wd + 1] |= m >> (64u - sh);
                 }
-                out_at += (uint64_t)__popcll(m);
             }
         }
         pos += tot;
-        __builtin_amdgcn_wave_barrier();
     }
-    if (!EMIT) {
-        const uint64_t f = wave_sum_u64(found);
-        if (lane == 0) A.unit_edges[unit] = (uint32_t)f;
-        if (FP32) {
-            const uint64_t rc = wave_sum_u64(rechecks), dg = wave_sum_u64(disagree);
-            if (lane == 0 && rc) atomicAdd(&A.stats[0], (unsigned long long)rc);
-            if (lane == 0 && dg) atomicAdd(&A.stats[1], (unsigned long long)dg);
+    wave_lds_sync();
+    A.bits[unit * 64 + lane] = s_bits[w][lane];
+    if (lane == 0) A.unit_edges[unit] = found;
+    if (FP32) {
+        const uint64_t rc = wave_sum_u64(rechecks), dg = wave_sum_u64(disagree);
+        if (lane == 0 && rc) atomicAdd(&A.stats[0], (unsigned long long)rc);
+        if (lane == 0 && dg) atomicAdd(&A.stats[1], (unsigned long long)dg);
+    }
+}
+
+// Emit pass: walk the unit exactly as the count pass did, take the decisions
+// from its bitmap, and write (min, max) original-index pairs, compacted per
+// 64-candidate round, at the unit's offset in the edge list.
+__global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
+    __shared__ uint32_t s_excl[4][64];
+    __shared__ uint32_t s_start[4][64];
+    __shared__ uint32_t s_qi[4][64];
+    __shared__ unsigned long long s_bits[4][65];
+
+    const Geo &g = A.geo;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t unit = (uint64_t)blockIdx.x * 4 + w;
+    if (unit >= A.n_units) return;
+    const uint32_t todo = A.unit_edges[unit];
+    if (todo == 0) return;
+    const UnitSetup u = unit_setup(A, unit, lane);
+    if (u.valid) s_qi[w][lane] = g.idx[u.v];
+    s_bits[w][lane] = A.bits[unit * 64 + lane];
+    if (lane == 0) s_bits[w][64] = 0ull;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t out_at = A.unit_edge_off[unit];
+    const uint64_t out_end = out_at + todo;
+
+    uint64_t pos = 0;
+    for (int j = u.jmin; j < g.B && out_at < out_end; ++j) {
+        uint32_t st, cnt, excl, tot;
+        slab_windows(u, j, st, cnt, excl, tot);
+        if (pos + tot <= u.r0) {
+            pos += tot;
+            continue;
         }
+        if (pos >= u.r1) break;
+        wave_lds_sync();
+        s_excl[w][lane] = excl;
+        s_start[w][lane] = st;
+        wave_lds_sync();
+        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
+        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
+        const uint32_t be = g.bs[j + 1], nj = be - g.bs[j];
+        for (uint32_t t0 = a; t0 < e && out_at < out_end; t0 += 64) {
+            const uint32_t o = (uint32_t)(pos + t0 - u.r0);
+            const uint32_t wd = o >> 6, sh = o & 63u;
+            uint64_t m = s_bits[w][wd] >> sh;
+            if (sh) m |= s_bits[w][wd + 1] << (64u - sh);
+            if (e - t0 < 64) m &= (~0ull >> (64u - (e - t0)));
+            if (!m) continue;
+            if ((m >> lane) & 1ull) {
+                const uint32_t t = t0 + lane;
+                const int l = find_window(s_excl[w], t);
+                uint32_t p = s_start[w][l] + (t - s_excl[w][l]);
+                if (p >= be) p -= nj;
+                if (p >= be) p = be - 1;
+                const uint32_t qi = s_qi[w][l], wi = g.idx[p];
+                const uint32_t lo = qi < wi ? qi : wi, hi = qi < wi ? wi : qi;
+                const uint64_t at = out_at + (uint64_t)__popcll(m & lt);
+                if (at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
+            }
+            out_at += (uint64_t)__popcll(m);
+        }
+        pos += tot;
     }
 }
 
@@ -308,17 +403,15 @@ static unsigned query_blocks(uint64_t units) { return (unsigned)((units + 3) / 4
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {
     if (!a.n_units) return;
     if (fp32)
-        hipLaunchKernelGGL((k_query<0, 1>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_count<1>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_query<0, 0>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_count<0>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
 }
 
 void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
+    (void)fp32;  // decisions come from the count pass's bitmap
     if (!a.n_units) return;
-    if (fp32)
-        hipLaunchKernelGGL((k_query<1, 1>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_query<1, 0>), dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_emit, dim3(query_blocks(a.n_units)), dim3(256), 0, st, a);
 }
 
 }  // namespace rhgk

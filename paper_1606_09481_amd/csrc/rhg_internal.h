@@ -14,11 +14,11 @@ enum Slot {
     S_KEYS, S_VALS, S_KEYS2, S_VALS2, S_HIST, S_SORTSCR,
     S_TH, S_RR, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
-    S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2,
+    S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART,
     S_COUNT
 };
 
-enum Ev { EV_KEYS0, EV_KEYS1, EV_SORT0, EV_SORT1, EV_TABLE1, EV_PLAN1, EV_COUNT0, EV_COUNT1, EV_SCAN1,
+enum Ev { EV_KEYS0, EV_KEYS1, EV_SORT0, EV_SORT1, EV_TABLE1, EV_PLAN0, EV_PLAN1, EV_COUNT0, EV_COUNT1, EV_SCAN1,
           EV_EMIT0, EV_EMIT1, EV_COUNT_ };
 
 struct SlotBuf {

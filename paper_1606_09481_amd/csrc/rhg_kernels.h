@@ -9,10 +9,13 @@ namespace rhgk {
 
 // a0 + a2: sample or read each point, find its slab (c_i <= r < c_{i+1},
 // r = R in the last), build the sort key (slab << 27 | q(theta)) and the
-// identity payload; count points per slab into hist[B] (zeroed here);
-// err |= 1 on a coordinate outside [0, 2pi] x [0, R] or non-finite.
-void keys(const rhgd::Source &src, int B, const double *c_host, uint32_t *keys, uint32_t *vals, uint32_t *hist,
-          int *err, hipStream_t st);
+// identity payload; err |= 1 on a coordinate outside [0, 2pi] x [0, R] or
+// non-finite (err zeroed here).
+void keys(const rhgd::Source &src, int B, const double *c_host, uint32_t *keys, uint32_t *vals, int *err,
+          hipStream_t st);
+
+// Slab starts bs[0..B] in the sorted keys (bs[B] = n).
+void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStream_t st);
 
 // a3: stable LSD radix sort of (keys, vals), `bits` low key bits, 8 per pass;
 // the result ends in (keys, vals); tmp buffers of n each; scratch from
@@ -42,7 +45,8 @@ void scan_u32(const uint32_t *in, uint64_t *out, uint64_t len, void *scratch, hi
 
 // Work units: units per batch = ceil(cand / UNIT).
 void units_per_batch(const uint64_t *batch_cand, uint64_t nb, uint64_t *nunits, hipStream_t st);
-void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint32_t *unit_batch, hipStream_t st);
+void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units, uint32_t *unit_batch,
+                     hipStream_t st);
 
 // a5 / a7 / a8: the band query.  count: edges per unit into unit_edges,
 // stats[0] += rechecks, stats[1] += filter/FP64 disagreements (exhaustive).
@@ -54,7 +58,8 @@ struct QueryArgs {
     const uint64_t *unit_off;   // per batch, first unit (exclusive scan of units)
     const uint32_t *unit_batch;
     uint64_t n_units;
-    uint32_t *unit_edges;          // count
+    uint32_t *unit_edges;          // count: edges per unit
+    unsigned long long *bits;      // count -> emit: 64 words of decisions per unit
     const uint64_t *unit_edge_off; // emit
     int2 *out;                     // emit
     uint64_t out_capacity;         // emit: pairs available at out

@@ -309,55 +309,23 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(keys2, uint32_t, S_KEYS2, n);
     RHG_BUF(vals2, uint32_t, S_VALS2, n);
     RHG_BUF(hist, uint32_t, S_HIST, MAX_BANDS + 8);
+    uint32_t *bstart = hist;
     int *err = (int *)(hist + MAX_BANDS + 4);
 
     RHG_HIP(hipEventRecord(c->ev[EV_KEYS0], st));
-    rhgk::keys(src, B, pl.c, keys, vals, hist, err, st);
+    rhgk::keys(src, B, pl.c, keys, vals, err, st);
     RHG_HIP(hipEventRecord(c->ev[EV_KEYS1], st));
-    // slab sizes -> layout
-    RHG_HIP(hipMemcpyAsync(c->pinned, hist, sizeof(uint32_t) * (MAX_BANDS + 8), hipMemcpyDeviceToHost, st));
-    RHG_HIP(hipStreamSynchronize(st));
-    const uint32_t *hh = (const uint32_t *)c->pinned;
-    if (hh[MAX_BANDS + 4] != 0) return RHG_EINVAL;  // coordinates out of range
 
-    Geo &g = pl.geo;
-    std::memset(&g, 0, sizeof(Geo));
-    g.n = (uint32_t)n;
-    g.B = B;
-    g.R = pl.R;
-    g.K = pl.K;
-    g.Kw = pl.K * (1.0 + 0x1p-30);
-    g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
-    g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
-    uint64_t acc = 0, wins = 0, btab_len = 0;
-    for (int j = 0; j < B; ++j) {
-        g.c[j] = pl.c[j];
-        g.shc[j] = std::sinh(pl.c[j]);
-        g.bs[j] = (uint32_t)acc;
-        g.winbase[j] = wins;
-        uint32_t nj = hh[j];
-        wins += (uint64_t)nj * (uint64_t)(B - j);
-        int bits = std::max(0, std::min(24, ceil_log2(nj) - 1));
-        g.bshift[j] = QBITS - bits;
-        g.bto[j] = (uint32_t)btab_len;
-        btab_len += (1ull << bits) + 1;
-        acc += nj;
-    }
-    g.c[B] = pl.c[B];
-    g.bs[B] = (uint32_t)acc;
-    g.winbase[B] = wins;
-    pl.windows = wins;
-    if (acc != n) return RHG_EDEVICE;
-
-    // sort
+    // sort, then the slab starts from the sorted keys
     const int key_bits = QBITS + std::max(1, ceil_log2((uint64_t)B));
     void *sort_scr = c->buf(S_SORTSCR, rhgk::sort_scratch_bytes(n));
     if (!sort_scr) return RHG_ENOMEM;
     RHG_HIP(hipEventRecord(c->ev[EV_SORT0], st));
     rhgk::radix_sort(keys, vals, keys2, vals2, sort_scr, n, key_bits, st);
+    rhgk::band_starts(keys, n, B, bstart, st);
     RHG_HIP(hipEventRecord(c->ev[EV_SORT1], st));
 
-    // table in sorted order + bucket index
+    // table in sorted order (needs no layout)
     RHG_BUF(th, double, S_TH, n);
     RHG_BUF(rr, double, S_RR, n);
     RHG_BUF(ep, double, S_EP, n);
@@ -373,6 +341,43 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         if (!ep32 || !em32 || !sh32) return RHG_ENOMEM;
     }
     rhgk::gather(src, vals, n, th, rr, ep, em, sh, hs, hc, ep32, em32, sh32, st);
+    RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
+
+    // slab sizes -> layout of windows and bucket index
+    RHG_HIP(hipMemcpyAsync(c->pinned, hist, sizeof(uint32_t) * (MAX_BANDS + 8), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipStreamSynchronize(st));
+    const uint32_t *hh = (const uint32_t *)c->pinned;
+    if (hh[MAX_BANDS + 4] != 0) return RHG_EINVAL;  // coordinates out of range
+
+    Geo &g = pl.geo;
+    std::memset(&g, 0, sizeof(Geo));
+    g.n = (uint32_t)n;
+    g.B = B;
+    g.R = pl.R;
+    g.K = pl.K;
+    g.Kw = pl.K * (1.0 + 0x1p-30);
+    g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
+    g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
+    uint64_t wins = 0, btab_len = 0;
+    if (hh[0] != 0 || hh[B] != n) return RHG_EDEVICE;
+    for (int j = 0; j < B; ++j) {
+        if (hh[j + 1] < hh[j]) return RHG_EDEVICE;
+        g.c[j] = pl.c[j];
+        g.shc[j] = std::sinh(pl.c[j]);
+        g.bs[j] = hh[j];
+        g.winbase[j] = wins;
+        const uint32_t nj = hh[j + 1] - hh[j];
+        wins += (uint64_t)nj * (uint64_t)(B - j);
+        int bits = std::max(0, std::min(24, ceil_log2(nj) - 1));
+        g.bshift[j] = QBITS - bits;
+        g.bto[j] = (uint32_t)btab_len;
+        btab_len += (1ull << bits) + 1;
+    }
+    g.c[B] = pl.c[B];
+    g.bs[B] = (uint32_t)n;
+    g.winbase[B] = wins;
+    pl.windows = wins;
+
     RHG_BUF(btab, uint32_t, S_BTAB, btab_len);
     g.keys = keys;
     g.idx = vals;
@@ -387,8 +392,8 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.em32 = em32;
     g.sh32 = sh32;
     g.btab = btab;
+    RHG_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     rhgk::bucket_index(g, btab, st);
-    RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
 
     // window plan and work units
     const uint64_t nb = (n + BATCH - 1) / BATCH;
@@ -417,9 +422,10 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(U, 1));
     RHG_BUF(ueoff, uint64_t, S_UEOFF, U + 1);
     RHG_BUF(stats, unsigned long long, S_STATS, 4);
+    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * 64);
     void *scan2 = c->buf(S_SCANSCR2, rhgk::scan_scratch_bytes(std::max<uint64_t>(U, 1)));
     if (!scan2) return RHG_ENOMEM;
-    rhgk::unit_batch_fill(uoff, nb, ubatch, st);
+    rhgk::unit_batch_fill(uoff, nb, U, ubatch, st);
     RHG_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, st));
 
     rhgk::QueryArgs &qa = pl.qa;
@@ -431,6 +437,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.unit_batch = ubatch;
     qa.n_units = U;
     qa.unit_edges = uedges;
+    qa.bits = bits;
     qa.unit_edge_off = ueoff;
     qa.stats = stats;
     qa.exhaustive = c->exhaustive;
@@ -462,7 +469,7 @@ rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
     RHG_HIP(hipGetLastError());
     // phase device times: each pair of events brackets only that phase's launches
     const int pairs[7][2] = {{EV_KEYS0, EV_KEYS1}, {EV_SORT0, EV_SORT1}, {EV_SORT1, EV_TABLE1},
-                             {EV_TABLE1, EV_PLAN1}, {EV_COUNT0, EV_COUNT1}, {EV_COUNT1, EV_SCAN1},
+                             {EV_PLAN0, EV_PLAN1}, {EV_COUNT0, EV_COUNT1}, {EV_COUNT1, EV_SCAN1},
                              {EV_EMIT0, EV_EMIT1}};
     double tot = 0;
     for (int k = 0; k < 7; ++k) {

@@ -115,17 +115,25 @@ void units_per_batch(const uint64_t *cand, uint64_t nb, uint64_t *nunits, hipStr
     if (nb) hipLaunchKernelGGL(k_units, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, cand, nb, nunits);
 }
 
-// unit_off[b] .. unit_off[b+1]-1 are the units of batch b.
-__global__ __launch_bounds__(256) void k_unit_fill(const uint64_t *unit_off, uint64_t nb, uint32_t *unit_batch) {
-    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    for (uint64_t u = unit_off[b]; u < unit_off[b + 1]; ++u) unit_batch[u] = (uint32_t)b;
+// unit_off[b] .. unit_off[b+1]-1 are the units of batch b: unit u belongs to
+// the last batch b with unit_off[b] <= u.
+__global__ __launch_bounds__(256) void k_unit_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units,
+                                                   uint32_t *unit_batch) {
+    uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    uint64_t lo = 0, hi = nb;  // search in unit_off[0..nb)
+    while (hi - lo > 1) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (unit_off[mid] <= u) lo = mid; else hi = mid;
+    }
+    unit_batch[u] = (uint32_t)lo;
 }
 
-void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint32_t *unit_batch, hipStream_t st) {
-    if (nb)
-        hipLaunchKernelGGL(k_unit_fill, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, unit_off, nb,
-                           unit_batch);
+void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units, uint32_t *unit_batch,
+                     hipStream_t st) {
+    if (nb && n_units)
+        hipLaunchKernelGGL(k_unit_fill, dim3((unsigned)((n_units + 255) / 256)), dim3(256), 0, st, unit_off, nb,
+                           n_units, unit_batch);
 }
 
 }  // namespace rhgk
