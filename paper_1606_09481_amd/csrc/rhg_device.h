@@ -5,14 +5,16 @@
 //   keys[n]   u32  (slab << 27) | q(theta): q is a monotone 27-bit
 //                  quantisation of the angle; the sort key and the search key
 //   idx[n]    u32  original point index of each sorted position
-//   th[n], rr[n]                         f64 angle and radius
-//   ep[n], em[n], sh[n], hs[n], hc[n]    f64 exp(r), exp(-r), sinh r,
-//                                        sin(theta/2), cos(theta/2)
-//   ep32[n], em32[n], sh32[n]            f32 shadows of ep, em, sh
+//   th[n], rr[n]     f64 angle and radius
+//   epm[n]           f64x2 (exp(r), exp(-r))
+//   sh[n]            f64 sinh r
+//   hsc[n]           f64x2 (sin(theta/2), cos(theta/2))
+//   f32[n]           f32x4 (exp(r), exp(-r), sinh r, 0) rounded once to FP32
 //   btab[]    u32  per slab j, 2^bits_j + 1 bucket starts over the top bits
 //                  of q (a direct-mapped index into the sorted slab)
 //   win[]     uint2 per (query, slab j >= slab(query)): circular position
-//                  window (start, count) in slab j
+//                  window (start, count) in slab j, slab-major
+//                  (win[winbase[j] + v], winbase[j] = sum_{j'<j} bs[j'+1])
 //   per 64-query batch: candidate totals and work units; per unit: edges.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -52,13 +54,18 @@ struct Geo {
     float klo32, khi32;       // FP32 filter thresholds (round-down / round-up of K(1 -+ mu))
     double c[MAX_BANDS + 1];  // slab boundaries
     double shc[MAX_BANDS + 1];  // sinh c_j
+    double epc[MAX_BANDS + 1];  // e^{c_j}
+    double emc[MAX_BANDS + 1];  // e^{-c_j}
+    double ishc[MAX_BANDS + 1]; // 1 / sinh c_j (j >= 1)
     uint32_t bs[MAX_BANDS + 1]; // slab start positions, bs[B] = n
-    uint64_t winbase[MAX_BANDS + 1];
+    uint64_t winbase[MAX_BANDS + 1];  // window (v, j) at winbase[j] + v
     uint32_t bto[MAX_BANDS + 1];  // bucket table offset of slab j
     int bshift[MAX_BANDS + 1];    // q >> bshift -> bucket
     const uint32_t *keys, *idx;
-    const double *th, *rr, *ep, *em, *sh, *hs, *hc;
-    const float *ep32, *em32, *sh32;
+    const double *th, *rr, *sh;
+    const double2 *epm;  // (exp(r), exp(-r))
+    const double2 *hsc;  // (sin(theta/2), cos(theta/2))
+    const float4 *f32;   // (exp(r), exp(-r), sinh r, 0) rounded to FP32 (FP32 filter only)
     const uint32_t *btab;
 };
 

@@ -26,8 +26,8 @@ void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *va
 
 // a1 + a3 gather: per sorted position, the point's angle, radius and table
 // (computed, or copied from the caller's table) in sorted order.
-void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double *rr, double *ep,
-            double *em, double *sh, double *hs, double *hc, float *ep32, float *em32, float *sh32, hipStream_t st);
+void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double *rr, double2 *epm,
+            double *sh, double2 *hsc, float4 *f32, hipStream_t st);
 
 // Same values in original order (for exporting the exact bits used).
 void point_values(const rhgd::Source &src, uint64_t n, double *th, double *rr, double *table5xn, hipStream_t st);
@@ -35,8 +35,9 @@ void point_values(const rhgd::Source &src, uint64_t n, double *th, double *rr, d
 // Slab bucket index: btab (geo.bto / geo.bshift layout).
 void bucket_index(const rhgd::Geo &geo, uint32_t *btab, hipStream_t st);
 
-// a4: windows of every (query, slab >= slab(query)); per-batch candidate totals.
-void plan(const rhgd::Geo &geo, uint2 *win, uint64_t *batch_cand, hipStream_t st);
+// a4: windows of every (query, slab >= slab(query)), stored slab-major;
+// per-batch candidate totals and per-batch slab segment offsets (B+1 each).
+void plan(const rhgd::Geo &geo, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off, hipStream_t st);
 
 // a6 scans: out[0..len] = exclusive prefix of in[0..len) (out[len] = total).
 size_t scan_scratch_bytes(uint64_t len);
@@ -55,11 +56,13 @@ struct QueryArgs {
     rhgd::Geo geo;
     const uint2 *win;
     const uint64_t *batch_cand;
+    const uint64_t *batch_slab_off;  // per batch, B+1 flattened slab segment offsets
     const uint64_t *unit_off;   // per batch, first unit (exclusive scan of units)
     const uint32_t *unit_batch;
+    const uint32_t *unit_order;    // execution order of units (sector-sorted), or null
     uint64_t n_units;
     uint32_t *unit_edges;          // count: edges per unit
-    unsigned long long *bits;      // count -> emit: 64 words of decisions per unit
+    unsigned long long *bits;      // count -> emit: 96 words of decisions per unit
     const uint64_t *unit_edge_off; // emit
     int2 *out;                     // emit
     uint64_t out_capacity;         // emit: pairs available at out
@@ -67,6 +70,9 @@ struct QueryArgs {
     int exhaustive;
 };
 void query_count(const QueryArgs &a, int fp32, hipStream_t st);
+// Sector-sorted execution order of the units into id (key/key_tmp/id_tmp: n_units each).
+void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_tmp, uint32_t *id_tmp,
+                void *sort_scratch, hipStream_t st);
 void query_emit(const QueryArgs &a, int fp32, hipStream_t st);
 
 }  // namespace rhgk

@@ -328,19 +328,15 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     // table in sorted order (needs no layout)
     RHG_BUF(th, double, S_TH, n);
     RHG_BUF(rr, double, S_RR, n);
-    RHG_BUF(ep, double, S_EP, n);
-    RHG_BUF(em, double, S_EM, n);
+    RHG_BUF(epm, double2, S_EP, n);
     RHG_BUF(sh, double, S_SH, n);
-    RHG_BUF(hs, double, S_HS, n);
-    RHG_BUF(hc, double, S_HC, n);
-    float *ep32 = nullptr, *em32 = nullptr, *sh32 = nullptr;
+    RHG_BUF(hsc, double2, S_HS, n);
+    float4 *f32 = nullptr;
     if (pl.fp32) {
-        ep32 = (float *)c->buf(S_EP32, sizeof(float) * n);
-        em32 = (float *)c->buf(S_EM32, sizeof(float) * n);
-        sh32 = (float *)c->buf(S_SH32, sizeof(float) * n);
-        if (!ep32 || !em32 || !sh32) return RHG_ENOMEM;
+        f32 = (float4 *)c->buf(S_EP32, sizeof(float4) * n);
+        if (!f32) return RHG_ENOMEM;
     }
-    rhgk::gather(src, vals, n, th, rr, ep, em, sh, hs, hc, ep32, em32, sh32, st);
+    rhgk::gather(src, vals, n, th, rr, epm, sh, hsc, f32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
 
     // slab sizes -> layout of windows and bucket index
@@ -364,10 +360,13 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         if (hh[j + 1] < hh[j]) return RHG_EDEVICE;
         g.c[j] = pl.c[j];
         g.shc[j] = std::sinh(pl.c[j]);
+        g.epc[j] = std::exp(pl.c[j]);
+        g.emc[j] = std::exp(-pl.c[j]);
+        g.ishc[j] = j > 0 ? 1.0 / g.shc[j] : 0.0;
         g.bs[j] = hh[j];
         g.winbase[j] = wins;
         const uint32_t nj = hh[j + 1] - hh[j];
-        wins += (uint64_t)nj * (uint64_t)(B - j);
+        wins += hh[j + 1];  // queries of slabs <= j each have a window in slab j
         int bits = std::max(0, std::min(24, ceil_log2(nj) - 1));
         g.bshift[j] = QBITS - bits;
         g.bto[j] = (uint32_t)btab_len;
@@ -383,14 +382,10 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.idx = vals;
     g.th = th;
     g.rr = rr;
-    g.ep = ep;
-    g.em = em;
+    g.epm = epm;
     g.sh = sh;
-    g.hs = hs;
-    g.hc = hc;
-    g.ep32 = ep32;
-    g.em32 = em32;
-    g.sh32 = sh32;
+    g.hsc = hsc;
+    g.f32 = f32;
     g.btab = btab;
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     rhgk::bucket_index(g, btab, st);
@@ -399,12 +394,13 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     const uint64_t nb = (n + BATCH - 1) / BATCH;
     RHG_BUF(win, uint2, S_WIN, std::max<uint64_t>(wins, 1));
     RHG_BUF(bcand, uint64_t, S_BCAND, nb);
+    RHG_BUF(bsoff, uint64_t, S_BANDSTART, nb * (uint64_t)(B + 1));
     RHG_BUF(boff, uint64_t, S_BOFF, nb + 1);
     RHG_BUF(nunits, uint64_t, S_NUNITS, nb);
     RHG_BUF(uoff, uint64_t, S_UOFF, nb + 1);
     void *scan_scr = c->buf(S_SCANSCR, rhgk::scan_scratch_bytes(std::max<uint64_t>(nb, 1ull << 22)));
     if (!scan_scr) return RHG_ENOMEM;
-    rhgk::plan(g, win, bcand, st);
+    rhgk::plan(g, win, bcand, bsoff, st);
     rhgk::scan_u64(bcand, boff, nb, scan_scr, st);
     rhgk::units_per_batch(bcand, nb, nunits, st);
     rhgk::scan_u64(nunits, uoff, nb, scan_scr, st);
@@ -422,9 +418,10 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(U, 1));
     RHG_BUF(ueoff, uint64_t, S_UEOFF, U + 1);
     RHG_BUF(stats, unsigned long long, S_STATS, 4);
-    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * 64);
+    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * 96);  // rhgk bitmap words per unit
     void *scan2 = c->buf(S_SCANSCR2, rhgk::scan_scratch_bytes(std::max<uint64_t>(U, 1)));
     if (!scan2) return RHG_ENOMEM;
+    RHG_HIP(hipEventRecord(c->ev[EV_COUNT0], st));  // count phase: unit bookkeeping + order + count
     rhgk::unit_batch_fill(uoff, nb, U, ubatch, st);
     RHG_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, st));
 
@@ -433,6 +430,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.geo = g;
     qa.win = win;
     qa.batch_cand = bcand;
+    qa.batch_slab_off = bsoff;
     qa.unit_off = uoff;
     qa.unit_batch = ubatch;
     qa.n_units = U;
@@ -441,7 +439,15 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.unit_edge_off = ueoff;
     qa.stats = stats;
     qa.exhaustive = c->exhaustive;
-    RHG_HIP(hipEventRecord(c->ev[EV_COUNT0], st));
+    RHG_BUF(ukey, uint32_t, S_UKEY, std::max<uint64_t>(U, 1));
+    RHG_BUF(uorder, uint32_t, S_UORDER, std::max<uint64_t>(U, 1));
+    RHG_BUF(ukey2, uint32_t, S_UKEY2, std::max<uint64_t>(U, 1));
+    RHG_BUF(uorder2, uint32_t, S_UORDER2, std::max<uint64_t>(U, 1));
+    void *usort = c->buf(S_SORTSCR2, rhgk::sort_scratch_bytes(std::max<uint64_t>(U, 1)));
+    if (!usort) return RHG_ENOMEM;
+    qa.unit_order = nullptr;
+    rhgk::unit_order(qa, ukey, uorder, ukey2, uorder2, usort, st);
+    qa.unit_order = uorder;
     rhgk::query_count(qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
     rhgk::scan_u32(uedges, ueoff, U, scan2, st);
