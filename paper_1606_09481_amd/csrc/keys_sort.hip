@@ -36,7 +36,7 @@ void keys(const Source &src, int B, const double *c_host, uint32_t *k, uint32_t 
     BandsArg ba;
     ba.B = B;
     for (int j = 0; j <= B; ++j) ba.c[j] = c_host[j];
-    hipMemsetAsync(err, 0, sizeof(int), st);
+    (void)hipMemsetAsync(err, 0, sizeof(int), st);
     uint64_t blocks = (src.n + 255) / 256;
     if (blocks) hipLaunchKernelGGL(k_keys, dim3((unsigned)blocks), dim3(256), 0, st, src, ba, k, v, err);
 }
@@ -171,8 +171,8 @@ void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *va
         t = va; va = vb; vb = t;
     }
     if (ka != keys) {
-        hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-        hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     }
 }
 

@@ -326,9 +326,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 // rank = (windows starting before t0 + 64 i) - 1 + popcount(M_i & bits 0..k).
 // No per-candidate search.  Count and emit use different VT (register
 // pressure vs. loads in flight); the flattened order is the same.
-constexpr int VT_COUNT = 2;
-constexpr int VT_EMIT = 4;
-constexpr int VT_MAX = 4;
+#ifndef RHG_VT_COUNT
+#define RHG_VT_COUNT 2
+#endif
+#ifndef RHG_VT_EMIT
+#define RHG_VT_EMIT 4
+#endif
+constexpr int VT_COUNT = RHG_VT_COUNT;
+constexpr int VT_EMIT = RHG_VT_EMIT;
 
 template <int VT>
 __device__ __forceinline__ void step_starts(uint32_t *flags, int lane, bool nonempty, uint32_t excl, uint32_t t0,
@@ -346,9 +351,9 @@ __device__ __forceinline__ void step_starts(uint32_t *flags, int lane, bool none
 
 // Decision bitmap of a unit: each slab segment the unit covers starts on a
 // fresh 64-bit word, so the decisions of one 64-candidate round are exactly
-// one word (its ballot).  A unit of <= 4096 candidates over <= 32 segments
-// needs at most 64 + 31 words.
-constexpr int BITW = 96;
+// one word (its ballot).  A unit of <= UNIT candidates over <= 32 segments
+// needs at most UNIT/64 + 31 words.
+constexpr int BITW = (int)(UNIT / 64) + 32;
 
 __device__ __forceinline__ uint32_t position_of(uint2 we, uint32_t t, uint32_t be, uint32_t nj) {
     uint32_t p = we.x + (t - we.y);
@@ -586,31 +591,32 @@ __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
         for (uint32_t t0 = a; t0 < e && out_at < out_end; t0 += 64u * VT) {
             uint64_t M[VT];
             step_starts<VT>(s_flag[w], lane, ne, excl, t0, M);
+            // decision words of the sub-rounds (uniform: kept in scalar registers)
             uint64_t m[VT];
+#pragma unroll
+            for (int i = 0; i < VT; ++i) {
+                const uint64_t x = (t0 + 64u * i < e) ? s_bits[w][word + i] : 0ull;
+                m[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+            }
+            // all gathers first (unconditional, in-bounds dummy for lanes without an edge) ...
             uint32_t wi[VT], qi[VT];
             bool mine_[VT];
 #pragma unroll
             for (int i = 0; i < VT; ++i) {
-                const uint32_t ti0 = t0 + 64u * i;
-                m[i] = (ti0 < e) ? s_bits[w][word + i] : 0ull;
-                const uint32_t rk = base - 1u + (uint32_t)__popcll(M[i] & le);
+                const uint32_t rk = (base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
                 base += (uint32_t)__popcll(M[i]);
                 mine_[i] = (m[i] >> lane) & 1ull;
-                wi[i] = 0u;
-                qi[i] = 0u;
-                if (mine_[i]) {
-                    const uint32_t p = position_pb(s_pb[w][rk], ti0 + lane, be, nj);
-                    qi[i] = s_qi[w][rk];
-                    wi[i] = ld<WIDE>(g.idx, p);
-                }
+                const uint32_t p = mine_[i] ? position_pb(s_pb[w][rk], t0 + 64u * i + lane, be, nj) : be - 1u;
+                qi[i] = s_qi[w][rk];
+                wi[i] = ld<WIDE>(g.idx, p);
             }
+            // ... then all stores back to back
 #pragma unroll
             for (int i = 0; i < VT; ++i) {
-                if (mine_[i]) {
-                    const uint32_t lo = qi[i] < wi[i] ? qi[i] : wi[i], hi = qi[i] < wi[i] ? wi[i] : qi[i];
-                    const uint64_t at = out_at + (uint64_t)__popcll(m[i] & lt);
-                    if (at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
-                }
+                const uint32_t lo = qi[i] < wi[i] ? qi[i] : wi[i], hi = qi[i] < wi[i] ? wi[i] : qi[i];
+                const uint64_t at = out_at + (uint64_t)__popcll(m[i] & lt);
+                if (mine_[i] && at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
                 out_at += (uint64_t)__popcll(m[i]);
             }
             word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;

@@ -31,7 +31,11 @@ constexpr double HALF_PI = 1.5707963267948966;
 constexpr double QSCALE = 134217728.0 / TWO_PI;  // 2^27 / fl(2 pi)
 constexpr int WAVE = 64;
 constexpr int BATCH = 64;        // queries per batch (one wavefront)
-constexpr uint32_t UNIT = 4096;  // candidates per work unit (upper bound)
+#ifndef RHG_UNIT
+#define RHG_UNIT 4096
+#endif
+constexpr uint32_t UNIT = RHG_UNIT;  // candidates per work unit (upper bound)
+constexpr uint32_t BITMAP_WORDS = UNIT / 64 + 32;  // decision bitmap words per unit
 
 enum SrcMode { SRC_SEED = 0, SRC_COORDS = 1, SRC_TABLE = 2 };
 

@@ -62,7 +62,7 @@ struct QueryArgs {
     const uint32_t *unit_order;    // execution order of units (sector-sorted), or null
     uint64_t n_units;
     uint32_t *unit_edges;          // count: edges per unit
-    unsigned long long *bits;      // count -> emit: 96 words of decisions per unit
+    unsigned long long *bits;      // count -> emit: BITMAP_WORDS words of decisions per unit
     const uint64_t *unit_edge_off; // emit
     int2 *out;                     // emit
     uint64_t out_capacity;         // emit: pairs available at out

@@ -89,7 +89,7 @@ size_t scan_scratch_bytes(uint64_t len) {
 template <typename T>
 static void scan_impl(const T *in, uint64_t *out, uint64_t len, void *scratch, hipStream_t st) {
     if (len == 0) {
-        hipMemsetAsync(out, 0, sizeof(uint64_t), st);
+        (void)hipMemsetAsync(out, 0, sizeof(uint64_t), st);
         return;
     }
     uint64_t ntiles = (len + SC_TILE - 1) / SC_TILE;
