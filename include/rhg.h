@@ -214,7 +214,25 @@ rhg_status rhg_server_submit(rhg_server *s, const rhg_params *params, uint64_t *
  * (caller frees it); latency_ms the time from submit to device completion.
  * A request that failed returns its error here. */
 rhg_status rhg_server_wait(rhg_server *s, uint64_t ticket, int timeout_ms, rhg_graph **out, double *latency_ms);
-/* Stop accepting, finish or fail pending requests, release everything. */
+/* Server counters:
+ *   completed    requests finished (success or error)
+ *   batched      requests run inside a shared one-launch group of small requests
+ *   groups       such launches
+ *   fallbacks    grouped requests that outgrew their preallocated scratch or
+ *                output slice and were rerun on the multi-launch path
+ *   peak_bytes   highest admitted estimated memory in flight
+ *   budget_bytes the admission budget */
+typedef struct {
+    uint64_t completed;
+    uint64_t batched;
+    uint64_t groups;
+    uint64_t fallbacks;
+    uint64_t peak_bytes;
+    uint64_t budget_bytes;
+} rhg_server_stats;
+rhg_status rhg_server_counters(rhg_server *s, rhg_server_stats *out);
+/* Stop accepting, finish pending requests, release everything (results never
+ * waited for are freed). */
 void rhg_server_destroy(rhg_server *s);
 
 /* Static string for a status code. */

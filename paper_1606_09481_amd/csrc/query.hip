@@ -29,345 +29,20 @@
 // the emit pass walks the unit identically, reads the map instead of
 // re-testing, and writes the pairs compacted per 64-candidate round, so the
 // edge order is deterministic.
-#include "rhg_kernels.h"
+#include "query_dev.h"
 
 namespace rhgk {
 using namespace rhgd;
 
-// Half-width of the window of query v in slab j >= 1.  The bound is
-//   s = (Kw - cosh(r_v - c_j)) / (2 sinh r_v sinh c_j),  half-width 2 asin(sqrt s),
-// with cosh(r_v - c_j) = (e^{r_v} e^{-c_j} + e^{-r_v} e^{c_j}) / 2 from the
-// point's table and per-slab constants, and the division by per-point and
-// per-slab reciprocals: every rounding here is a few u relative, far inside
-// the 2^-30 K slack of Kw.  asin and sqrt run in FP32 on the rounded s (s in
-// (0, 1/2)): at most a few ulp_32 relative, covered by the 2^-16 relative
-// widening; values of s below FP32 range give half-widths far below the
-// 2^-44 rad absolute widening.  Returns 1 for a whole slab (half-width >= pi/2).
-struct QPlan {
-    double hep, hem, inv2sh;  // 0.5 e^{r_v}, 0.5 e^{-r_v}, 1 / (2 sinh r_v) (0: whole slabs)
-};
-
-__device__ __forceinline__ int half_width(const Geo &g, const QPlan &q, int j, double *delta) {
-    if (!(q.inv2sh > 0.0)) return 1;
-    const double C = q.hep * g.emc[j] + q.hem * g.epc[j];
-    double s = ((g.Kw - C) * q.inv2sh) * g.ishc[j];
-    if (!(s < 0.5)) return 1;  // sin^2(D/2) >= 1/2  <=>  D >= pi/2
-    if (s < 0.0) s = 0.0;
-    const float d32 = 2.0f * asinf(sqrtf((float)s));
-    const double d = (double)d32 * (1.0 + 0x1p-16) + 0x1p-44;
-    if (!(d < HALF_PI)) return 1;
-    *delta = d;
-    return 0;
-}
-
-// First position of slab j with quantised angle >= x / > x: a direct-mapped
-// bucket lookup, then a binary search inside the bucket.
-__device__ __forceinline__ uint32_t lower_pos(const Geo &g, int j, uint32_t x) {
-    const uint32_t *T = g.btab + g.bto[j];
-    uint32_t b = x >> g.bshift[j];
-    uint32_t lo = T[b], hi = T[b + 1];
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((g.keys[mid] & QMASK) < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-__device__ __forceinline__ uint32_t upper_pos(const Geo &g, int j, uint32_t x) {
-    const uint32_t *T = g.btab + g.bto[j];
-    uint32_t b = x >> g.bshift[j];
-    uint32_t lo = T[b], hi = T[b + 1];
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((g.keys[mid] & QMASK) <= x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-// Both ends of an angular range at once (independent loads in flight together).
-__device__ __forceinline__ uint2 range_pos(const Geo &g, int j, uint32_t xlo, uint32_t xhi) {
-    const uint32_t *T = g.btab + g.bto[j];
-    const int sh = g.bshift[j];
-    const uint32_t bl = xlo >> sh, bh = xhi >> sh;
-    uint32_t l0 = T[bl], l1 = T[bl + 1], h0 = T[bh], h1 = T[bh + 1];
-    while (l0 < l1 || h0 < h1) {
-        const uint32_t ml = (l0 + l1) >> 1, mh = (h0 + h1) >> 1;
-        const uint32_t kl = (l0 < l1) ? (g.keys[ml] & QMASK) : 0u;
-        const uint32_t kh = (h0 < h1) ? (g.keys[mh] & QMASK) : 0u;
-        if (l0 < l1) {
-            if (kl < xlo) l0 = ml + 1; else l1 = ml;
-        }
-        if (h0 < h1) {
-            if (kh <= xhi) h0 = mh + 1; else h1 = mh;
-        }
-    }
-    return make_uint2(l0, h0);
-}
-
-// Circular window (start, count) of sorted query s (slab i) in slab j >= i.
-__device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j, double thv, uint32_t qv) {
-    const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
-    if (nj == 0) return make_uint2(bs, 0u);
-    double delta = 0.0;
-    const int whole = (j == 0) ? 1 : half_width(g, qp, j, &delta);
-    if (j == i) {
-        uint32_t cnt;
-        if (whole) {
-            if (qv < QHALF) {
-                cnt = upper_pos(g, j, qv + QHALF) - s - 1;
-            } else {
-                cnt = (be - s - 1) + (lower_pos(g, j, qv - QHALF) - bs);
-            }
-        } else {
-            double hi = thv + delta;
-            if (hi < TWO_PI) {
-                cnt = upper_pos(g, j, qang(hi)) - s - 1;
-            } else {
-                cnt = (be - s - 1) + (upper_pos(g, j, qang(hi - TWO_PI)) - bs);
-            }
-        }
-        return make_uint2(s + 1, cnt);
-    }
-    if (whole) return make_uint2(bs, nj);
-    double lo = thv - delta, hi = thv + delta;
-    uint2 r;
-    if (lo < 0.0) {
-        r = range_pos(g, j, qang(lo + TWO_PI), qang(hi));
-        return make_uint2(r.x, (be - r.x) + (r.y - bs));
-    }
-    if (hi >= TWO_PI) {
-        r = range_pos(g, j, qang(lo), qang(hi - TWO_PI));
-        return make_uint2(r.x, (be - r.x) + (r.y - bs));
-    }
-    r = range_pos(g, j, qang(lo), qang(hi));
-    return make_uint2(r.x, r.y - r.x);
-}
-
-// Windows are stored slab-major: window (v, j) of sorted query v (slab(v) <= j)
-// at win[winbase[j] + v], so the 64 queries of a batch read one slab's
-// windows with one coalesced load.
 __global__ __launch_bounds__(256) void k_plan(Geo g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off) {
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t b = s >> 6;
-    const uint32_t nb = (g.n + 63) / 64;
-    if (b >= nb) return;  // whole wavefronts past the last batch
-    const bool valid = s < g.n;
-    const int jmin = (int)(g.keys[b * BATCH] >> QBITS);
-    int i = g.B;
-    uint32_t qv = 0;
-    double thv = 0.0;
-    QPlan qp{0.0, 0.0, 0.0};
-    if (valid) {
-        const uint32_t key = g.keys[s];
-        i = (int)(key >> QBITS);
-        qv = key & QMASK;
-        thv = g.th[s];
-        const double2 e = g.epm[s];
-        const double shv = g.sh[s];
-        qp.hep = 0.5 * e.x;
-        qp.hem = 0.5 * e.y;
-        qp.inv2sh = (shv > 0.0) ? 1.0 / (2.0 * shv) : 0.0;
-    }
-    uint64_t *row = batch_slab_off + (uint64_t)b * (g.B + 1);
-    const int lane = threadIdx.x & 63;
-    for (int j = lane; j <= jmin && j <= g.B; j += 64) row[j] = 0;
-    uint64_t acc = 0;
-    for (int j = jmin; j < g.B; ++j) {
-        uint32_t cnt = 0;
-        if (valid && j >= i) {
-            const uint2 x = window(g, qp, s, i, j, thv, qv);
-            win[g.winbase[j] + s] = x;
-            cnt = x.y;
-        }
-        acc += wave_sum_u64(cnt);
-        if (lane == 0) row[j + 1] = acc;
-    }
-    if (lane == 0) batch_cand[b] = acc;
+    const uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (b >= (g.n + 63) / 64) return;  // whole wavefronts past the last batch
+    plan_batch(g, win, batch_cand, batch_slab_off, b, threadIdx.x & 63);
 }
 
 void plan(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off, hipStream_t st) {
     if (!g.n) return;
     hipLaunchKernelGGL(k_plan, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
-}
-
-// ---------------------------------------------------------------------------
-// Distance test (Eq. 3).  The canonical FP64 value is
-//   V = 0.5 (ep_u em_w + em_u ep_w) + 2 (sh_u sh_w) d^2,  d = hs_u hc_w - hc_u hs_w,
-// one rounding per operation.  The query-side halves/doubles (0.5 ep_u,
-// 0.5 em_u, 2 sh_u) are exact power-of-two scalings, so
-//   V = (hep_u em_w + hem_u ep_w) + (sh2_u sh_w) d^2
-// rounds to the same bits with two multiplications fewer.
-// FP32 filter: with d computed in FP64 and rounded once, every FP32 operand
-// and operation adds at most a relative u32 = 2^-24 to a sum of positive
-// terms, so |V32 - W| <= gamma_8 W and |V64 - W| <= gamma_6(2^-53) W for the
-// exact W of the table values; with mu = 2^-20 > gamma_8 + gamma_6,
-// V32 <= RD(K(1-mu)) implies V64 < K and V32 >= RU(K(1+mu)) implies V64 >= K.
-// Pairs between the two thresholds are decided by V64.
-// ---------------------------------------------------------------------------
-struct Qv {
-    double hep, hem, sh2, hs, hc;
-    float hep32, hem32, sh2_32;
-};
-
-// Candidate operands, loaded for several candidates before any is decided so
-// that their memory latencies overlap.
-struct Cand {
-    double2 hw;  // (sin, cos) of theta_w / 2
-    double2 ew;  // (exp r_w, exp -r_w)        FP64 form
-    double sh;   // sinh r_w                   FP64 form
-    float4 f;    // FP32 shadows               FP32 form
-};
-
-// Element i of a table column.  Unless WIDE, the byte offset is formed in 32
-// bits (tables under 4 GiB, n < 2^28), which lets the load take the column
-// base from scalar registers with a 32-bit per-lane offset.
-template <bool WIDE, typename T>
-__device__ __forceinline__ T ld(const T *base, uint32_t i) {
-    if (WIDE) return base[i];
-    return *(const T *)((const char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
-}
-
-template <int FP32, bool WIDE>
-__device__ __forceinline__ void load_cand(const Geo &g, uint32_t p, Cand &c) {
-    c.hw = ld<WIDE>(g.hsc, p);
-    if (!FP32) {
-        c.ew = ld<WIDE>(g.epm, p);
-        c.sh = ld<WIDE>(g.sh, p);
-    } else {
-        c.f = ld<WIDE>(g.f32, p);
-    }
-}
-
-// Returns bit 0 = edge, bit 1 = re-decided in FP64, bit 2 = FP32 decision
-// differed from FP64 (exhaustive self-check only).
-template <int FP32>
-__device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const Cand &c, uint32_t p, int exhaustive) {
-    const double d = q.hs * c.hw.y - q.hc * c.hw.x;
-    if (!FP32) {
-        const double a = q.hep * c.ew.y + q.hem * c.ew.x;
-        const double b = (q.sh2 * c.sh) * (d * d);
-        return (a + b) < g.K ? 1u : 0u;
-    } else {
-        const float d32 = (float)d;
-        const float a32 = q.hep32 * c.f.y + q.hem32 * c.f.x;
-        const float b32 = (q.sh2_32 * d32) * (c.f.z * d32);
-        const float v32 = a32 + b32;
-        const bool sure_in = v32 <= g.klo32, sure_out = v32 >= g.khi32;
-        if (sure_in || sure_out) {
-            if (!exhaustive) return sure_in ? 1u : 0u;
-        }
-        const double2 e = g.epm[p];
-        const double a = q.hep * e.y + q.hem * e.x;
-        const double b = (q.sh2 * g.sh[p]) * (d * d);
-        const uint32_t e64 = (a + b) < g.K ? 1u : 0u;
-        if (!(sure_in || sure_out)) return e64 | 2u;
-        const uint32_t f32dec = sure_in ? 1u : 0u;
-        return f32dec | (f32dec != e64 ? 4u : 0u);
-    }
-}
-
-// Per-unit setup shared by the count and emit passes: the unit's batch and
-// flattened range [r0, r1), the lane's query, and the first slab whose
-// segment reaches past r0 (from the batch's per-slab offsets).
-struct UnitSetup {
-    uint32_t b;
-    uint64_t r0, r1;
-    uint32_t v;
-    bool valid;
-    int iv, jstart;
-    uint64_t pos;  // flattened offset of slab jstart's segment
-};
-
-__device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
-    const Geo &g = A.geo;
-    UnitSetup u;
-    u.b = A.unit_batch[unit];
-    const uint64_t chunk = unit - A.unit_off[u.b];
-    u.r0 = chunk * UNIT;
-    const uint64_t bc = A.batch_cand[u.b];
-    u.r1 = (u.r0 + UNIT < bc) ? u.r0 + UNIT : bc;
-    u.v = u.b * BATCH + lane;
-    u.valid = u.v < g.n;
-    u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
-    const int jmin = (int)(g.keys[u.b * BATCH] >> QBITS);
-    // segments of slabs jmin..B-1 end at row[j+1]; skip those ending at or before r0
-    const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
-    const int k = jmin + lane;
-    const bool done = k < g.B && row[k + 1] <= u.r0;
-    u.jstart = jmin + __popcll(__ballot(done));
-    u.pos = (u.jstart < g.B) ? row[u.jstart] : bc;
-    return u;
-}
-
-// Lane's window in slab j (0 count if none), scanned over the wavefront.
-__device__ __forceinline__ void slab_windows(const Geo &g, const QueryArgs &A, const UnitSetup &u, int j,
-                                             uint32_t &st, uint32_t &cnt, uint32_t &excl, uint32_t &tot) {
-    st = 0;
-    cnt = 0;
-    if (u.valid && j >= u.iv) {
-        const uint2 x = A.win[g.winbase[j] + u.v];
-        st = x.x;
-        cnt = x.y;
-    }
-    const uint32_t incl = wave_incl_scan_u32(cnt);
-    tot = wave_bcast_u32(incl, 63);
-    excl = incl - cnt;
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Window lookup for one step of VT x 64 candidates of a slab segment.  The
-// non-empty windows of the slab are numbered in lane order (their rank);
-// window r covers flattened candidates [excl_r, excl_r + cnt_r).  Each window
-// that starts inside [t0, t0 + VT*64) flags its start slot; the ballot M_i of
-// the flags of sub-round i gives, for candidate t0 + 64 i + k,
-// rank = (windows starting before t0 + 64 i) - 1 + popcount(M_i & bits 0..k).
-// No per-candidate search.  Count and emit use different VT (register
-// pressure vs. loads in flight); the flattened order is the same.
-#ifndef RHG_VT_COUNT
-#define RHG_VT_COUNT 2
-#endif
-#ifndef RHG_VT_EMIT
-#define RHG_VT_EMIT 4
-#endif
-constexpr int VT_COUNT = RHG_VT_COUNT;
-constexpr int VT_EMIT = RHG_VT_EMIT;
-
-template <int VT>
-__device__ __forceinline__ void step_starts(uint32_t *flags, int lane, bool nonempty, uint32_t excl, uint32_t t0,
-                                            uint64_t (&M)[VT]) {
-    if (nonempty && excl >= t0 && excl - t0 < 64u * VT) flags[excl - t0] = 1u;
-    wave_lds_sync();
-#pragma unroll
-    for (int i = 0; i < VT; ++i) {
-        const uint32_t f = flags[i * 64 + lane];
-        flags[i * 64 + lane] = 0u;
-        M[i] = __ballot(f != 0u);
-    }
-    wave_lds_sync();
-}
-
-// Decision bitmap of a unit: each slab segment the unit covers starts on a
-// fresh 64-bit word, so the decisions of one 64-candidate round are exactly
-// one word (its ballot).  A unit of <= UNIT candidates over <= 32 segments
-// needs at most UNIT/64 + 31 words.
-constexpr int BITW = (int)(UNIT / 64) + 32;
-
-__device__ __forceinline__ uint32_t position_of(uint2 we, uint32_t t, uint32_t be, uint32_t nj) {
-    uint32_t p = we.x + (t - we.y);
-    if (p >= be) p -= nj;
-    if (p >= be) p = be - 1;  // unreachable for consistent windows; keeps reads in bounds
-    return p;
-}
-
-// Same with the window's (start - offset) precomputed: p = pb + t, wrapped once
-// at the slab end, clamped into the slab (unreachable for consistent windows).
-__device__ __forceinline__ uint32_t position_pb(uint32_t pb, uint32_t t, uint32_t be, uint32_t nj) {
-    uint32_t p = pb + t;
-    p = (p >= be) ? p - nj : p;
-    return min(p, be - 1u);
 }
 
 // Execution order of units.  Units are executed grouped by the angular
@@ -424,205 +99,22 @@ void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_t
     radix_sort(key, id, key_tmp, id_tmp, sort_scratch, a.n_units, SECTOR_BITS, st);
 }
 
-// Count pass: decide every candidate of the unit, record the decisions as
-// one bitmap word per 64-candidate round, count edges.
 template <int FP32, bool WIDE>
 __global__ __launch_bounds__(256) void k_count(QueryArgs A) {
-    constexpr int VT = VT_COUNT;
-    __shared__ uint32_t s_pb[4][64];    // per rank: start position - flattened offset
-    __shared__ uint32_t s_flag[4][64 * VT];
-    __shared__ double s_qd[4][5][64];   // per rank: query operands
-    __shared__ float s_qf[4][3][64];
-    __shared__ unsigned long long s_bits[4][BITW];
-
-    const Geo &g = A.geo;
+    __shared__ CountSmem sm[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t unit = exec_unit(A, w);
     if (unit == ~0ull) return;  // uniform per wavefront; no block-wide barriers below
-    const UnitSetup u = unit_setup(A, unit, lane);
-    Qv mine{};
-    if (u.valid) {
-        const double2 e = g.epm[u.v];
-        const double2 h = g.hsc[u.v];
-        mine.hep = 0.5 * e.x;
-        mine.hem = 0.5 * e.y;
-        mine.sh2 = 2.0 * g.sh[u.v];
-        mine.hs = h.x;
-        mine.hc = h.y;
-        if (FP32) {
-            const float4 f = g.f32[u.v];
-            mine.hep32 = 0.5f * f.x;
-            mine.hem32 = 0.5f * f.y;
-            mine.sh2_32 = 2.0f * f.z;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < VT; ++i) s_flag[w][i * 64 + lane] = 0u;
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-
-    uint64_t pos = u.pos;  // flattened offset of slab j's segment within the batch
-    uint32_t word = 0;     // next free bitmap word
-    uint32_t found = 0, rechecks = 0, disagree = 0;
-    for (int j = u.jstart; j < g.B && pos < u.r1; ++j) {
-        uint32_t st, cnt, excl, tot;
-        slab_windows(g, A, u, j, st, cnt, excl, tot);
-        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
-        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
-        const bool ne = cnt != 0u;
-        const uint64_t nem = __ballot(ne);
-        wave_lds_sync();
-        if (ne) {
-            const uint32_t rk = (uint32_t)__popcll(nem & lt);
-            s_pb[w][rk] = st - excl;
-            s_qd[w][0][rk] = mine.hep;
-            s_qd[w][1][rk] = mine.hem;
-            s_qd[w][2][rk] = mine.sh2;
-            s_qd[w][3][rk] = mine.hs;
-            s_qd[w][4][rk] = mine.hc;
-            if (FP32) {
-                s_qf[w][0][rk] = mine.hep32;
-                s_qf[w][1][rk] = mine.hem32;
-                s_qf[w][2][rk] = mine.sh2_32;
-            }
-        }
-        uint32_t base = (uint32_t)__popcll(__ballot(ne && excl < a));
-        const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
-        for (uint32_t t0 = a; t0 < e; t0 += 64u * VT) {
-            uint64_t M[VT];
-            step_starts<VT>(s_flag[w], lane, ne, excl, t0, M);
-            uint32_t p[VT], rk[VT];
-            bool act[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t t = t0 + 64u * i + lane;
-                act[i] = t < e;
-                rk[i] = base - 1u + (uint32_t)__popcll(M[i] & le);
-                base += (uint32_t)__popcll(M[i]);
-                p[i] = act[i] ? position_pb(s_pb[w][rk[i]], t, be, nj) : bs;
-            }
-            Cand c[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) load_cand<FP32, WIDE>(g, p[i], c[i]);
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                int flag = 0;
-                if (act[i]) {
-                    Qv q;
-                    q.hep = s_qd[w][0][rk[i]];
-                    q.hem = s_qd[w][1][rk[i]];
-                    q.sh2 = s_qd[w][2][rk[i]];
-                    q.hs = s_qd[w][3][rk[i]];
-                    q.hc = s_qd[w][4][rk[i]];
-                    if (FP32) {
-                        q.hep32 = s_qf[w][0][rk[i]];
-                        q.hem32 = s_qf[w][1][rk[i]];
-                        q.sh2_32 = s_qf[w][2][rk[i]];
-                    }
-                    const uint32_t r = edge_test<FP32>(g, q, c[i], p[i], A.exhaustive);
-                    flag = (int)(r & 1u);
-                    if (FP32) {
-                        rechecks += (r >> 1) & 1u;
-                        disagree += (r >> 2) & 1u;
-                    }
-                }
-                const uint64_t m = __ballot(flag);
-                found += (uint32_t)__popcll(m);
-                if (t0 + 64u * i < e && lane == 0) s_bits[w][word + i] = m;
-            }
-            word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
-        }
-        pos += tot;
-    }
-    wave_lds_sync();
-    for (uint32_t k = lane; k < word; k += 64) A.bits[unit * BITW + k] = s_bits[w][k];
-    if (lane == 0) A.unit_edges[unit] = found;
-    if (FP32) {
-        const uint64_t rc = wave_sum_u64(rechecks), dg = wave_sum_u64(disagree);
-        if (lane == 0 && rc) atomicAdd(&A.stats[0], (unsigned long long)rc);
-        if (lane == 0 && dg) atomicAdd(&A.stats[1], (unsigned long long)dg);
-    }
+    count_unit<FP32, WIDE>(A, unit, lane, sm[w]);
 }
 
-// Emit pass: walk the unit exactly as the count pass did, take the decisions
-// from its bitmap, and write (min, max) original-index pairs, compacted per
-// 64-candidate round, at the unit's offset in the edge list.
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
-    constexpr int VT = VT_EMIT;
-    __shared__ uint32_t s_pb[4][64];
-    __shared__ uint32_t s_flag[4][64 * VT];
-    __shared__ uint32_t s_qi[4][64];
-    __shared__ unsigned long long s_bits[4][BITW];
-
-    const Geo &g = A.geo;
+    __shared__ EmitSmem sm[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t unit = exec_unit(A, w);
     if (unit == ~0ull) return;
-    const uint32_t todo = A.unit_edges[unit];
-    if (todo == 0) return;
-    const UnitSetup u = unit_setup(A, unit, lane);
-    const uint32_t myqi = u.valid ? g.idx[u.v] : 0u;
-    for (int k = lane; k < BITW; k += 64) s_bits[w][k] = A.bits[unit * BITW + k];
-#pragma unroll
-    for (int i = 0; i < VT; ++i) s_flag[w][i * 64 + lane] = 0u;
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t out_at = A.unit_edge_off[unit];
-    const uint64_t out_end = out_at + todo;
-
-    uint64_t pos = u.pos;
-    uint32_t word = 0;
-    for (int j = u.jstart; j < g.B && pos < u.r1 && out_at < out_end; ++j) {
-        uint32_t st, cnt, excl, tot;
-        slab_windows(g, A, u, j, st, cnt, excl, tot);
-        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
-        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
-        const bool ne = cnt != 0u;
-        const uint64_t nem = __ballot(ne);
-        wave_lds_sync();
-        if (ne) {
-            const uint32_t rk = (uint32_t)__popcll(nem & lt);
-            s_pb[w][rk] = st - excl;
-            s_qi[w][rk] = myqi;
-        }
-        uint32_t base = (uint32_t)__popcll(__ballot(ne && excl < a));
-        const uint32_t be = g.bs[j + 1], nj = be - g.bs[j];
-        for (uint32_t t0 = a; t0 < e && out_at < out_end; t0 += 64u * VT) {
-            uint64_t M[VT];
-            step_starts<VT>(s_flag[w], lane, ne, excl, t0, M);
-            // decision words of the sub-rounds (uniform: kept in scalar registers)
-            uint64_t m[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint64_t x = (t0 + 64u * i < e) ? s_bits[w][word + i] : 0ull;
-                m[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-            }
-            // all gathers first (unconditional, in-bounds dummy for lanes without an edge) ...
-            uint32_t wi[VT], qi[VT];
-            bool mine_[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t rk = (base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
-                base += (uint32_t)__popcll(M[i]);
-                mine_[i] = (m[i] >> lane) & 1ull;
-                const uint32_t p = mine_[i] ? position_pb(s_pb[w][rk], t0 + 64u * i + lane, be, nj) : be - 1u;
-                qi[i] = s_qi[w][rk];
-                wi[i] = ld<WIDE>(g.idx, p);
-            }
-            // ... then all stores back to back
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t lo = qi[i] < wi[i] ? qi[i] : wi[i], hi = qi[i] < wi[i] ? wi[i] : qi[i];
-                const uint64_t at = out_at + (uint64_t)__popcll(m[i] & lt);
-                if (mine_[i] && at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
-                out_at += (uint64_t)__popcll(m[i]);
-            }
-            word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
-        }
-        pos += tot;
-    }
+    emit_unit<WIDE>(A, unit, lane, sm[w]);
 }
 
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {

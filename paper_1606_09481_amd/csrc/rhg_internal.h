@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include <memory>
+
 #include "../../include/rhg.h"
 #include "rhg_device.h"
 #include "rhg_kernels.h"
@@ -82,6 +84,7 @@ struct Graph {
     Request rq;
     Plan pl;
     int32_t *edges = nullptr;
+    std::shared_ptr<void> edge_owner;  // set when edges are a slice of a shared buffer
     double *d_theta = nullptr, *d_r = nullptr, *d_table = nullptr;
 };
 
@@ -97,6 +100,14 @@ inline uint64_t algorithmic_bytes(const Plan &p) {
 }
 
 rhg_status describe(const Request &rq, Plan &pl);
+rhg_status request_from_params(const rhg_params *p, Request &rq);
+// Average degree the model approximation gives for (n, alpha, R) (n when alpha <= 1/2).
+double expected_degree(uint64_t n, double alpha, double R);
+void geo_static(const Plan &pl, rhgd::Geo &g);
+int key_bits_for(int B);
+int ceil_log2(uint64_t x);
+rhg_status hip_status(hipError_t e);
+void graph_release(Graph *g);
 rhg_status run_count(Ctx *c, const Request &rq, Plan &pl);
 rhg_status run_emit(Ctx *c, Plan &pl, int2 *out);
 rhg_status generate(Ctx *c, const Request &rq, bool emit, Graph **out, uint64_t *m_out);

@@ -75,4 +75,34 @@ void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_t
                 void *sort_scratch, hipStream_t st);
 void query_emit(const QueryArgs &a, int fp32, hipStream_t st);
 
+// One-launch generation of small requests: one workgroup per descriptor.
+// The host fills src, the static geometry (n, B, R, K, Kw, FP32 thresholds,
+// slab constants), fp32, key_bits and the scratch pointers with their
+// capacities; the device fills the rest.  status: 0 done, 1 scratch too
+// small (rerun on the multi-launch path), 2 output pool full.
+constexpr uint32_t SMALL_N = 16384;
+struct SmallDesc {
+    rhgd::Source src;
+    rhgd::Geo geo;
+    int fp32, key_bits;
+    uint32_t *keys, *vals, *keys2, *vals2;
+    double *th, *rr, *sh;
+    double2 *epm, *hsc;
+    float4 *f32;
+    uint32_t *btab;
+    uint64_t btab_cap;
+    uint2 *win;
+    uint64_t win_cap;
+    uint64_t *bcand, *boff, *nunits, *uoff, *bsoff;
+    uint32_t *ubatch, *uedges;
+    uint64_t *ueoff;
+    unsigned long long *bits;
+    uint64_t unit_cap;
+    unsigned long long *stats;  // [rechecks, disagreements]
+    uint64_t m, candidates, windows, out_off, rechecks;
+    int status;  // -1 pending, 0 done, 1 scratch too small, 2 output pool full, 3 invalid
+};
+void small_group(SmallDesc *descs, int count, int2 *pool, unsigned long long *pool_used, uint64_t pool_cap,
+                 hipStream_t st);
+
 }  // namespace rhgk

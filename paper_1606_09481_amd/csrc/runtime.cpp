@@ -232,7 +232,7 @@ extern "C" void rhg_ctx_destroy(rhg_ctx *ctx) {
 // ---------------------------------------------------------------------------
 namespace rhgi {
 
-static rhg_status hip_status(hipError_t e) {
+rhg_status hip_status(hipError_t e) {
     if (e == hipSuccess) return RHG_OK;
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? RHG_ENOMEM : RHG_EDEVICE;
@@ -248,7 +248,7 @@ static rhg_status hip_status(hipError_t e) {
     type *var = (type *)c->buf((slot), sizeof(type) * (size_t)(count));  \
     if (!var) return RHG_ENOMEM
 
-static int ceil_log2(uint64_t x) {
+int ceil_log2(uint64_t x) {
     int b = 0;
     while ((1ull << b) < x) ++b;
     return b;
@@ -285,6 +285,29 @@ static float round_up_f32(double x) {
     return f;
 }
 
+// Geometry that does not depend on the points: slab boundaries and their
+// sinh / exp / reciprocal constants, cosh R, the widened window threshold and
+// the FP32 filter thresholds.
+void geo_static(const Plan &pl, Geo &g) {
+    std::memset(&g, 0, sizeof(Geo));
+    g.n = (uint32_t)pl.n;
+    g.B = pl.B;
+    g.R = pl.R;
+    g.K = pl.K;
+    g.Kw = pl.K * (1.0 + 0x1p-30);
+    g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
+    g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
+    for (int j = 0; j <= pl.B; ++j) {
+        g.c[j] = pl.c[j];
+        g.shc[j] = std::sinh(pl.c[j]);
+        g.epc[j] = std::exp(pl.c[j]);
+        g.emc[j] = std::exp(-pl.c[j]);
+        g.ishc[j] = j > 0 ? 1.0 / g.shc[j] : 0.0;
+    }
+}
+
+int key_bits_for(int B) { return QBITS + std::max(1, ceil_log2((uint64_t)B)); }
+
 rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipSetDevice(c->device));
     const hipStream_t st = c->stream;
@@ -317,7 +340,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipEventRecord(c->ev[EV_KEYS1], st));
 
     // sort, then the slab starts from the sorted keys
-    const int key_bits = QBITS + std::max(1, ceil_log2((uint64_t)B));
+    const int key_bits = key_bits_for(B);
     void *sort_scr = c->buf(S_SORTSCR, rhgk::sort_scratch_bytes(n));
     if (!sort_scr) return RHG_ENOMEM;
     RHG_HIP(hipEventRecord(c->ev[EV_SORT0], st));
@@ -346,23 +369,11 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     if (hh[MAX_BANDS + 4] != 0) return RHG_EINVAL;  // coordinates out of range
 
     Geo &g = pl.geo;
-    std::memset(&g, 0, sizeof(Geo));
-    g.n = (uint32_t)n;
-    g.B = B;
-    g.R = pl.R;
-    g.K = pl.K;
-    g.Kw = pl.K * (1.0 + 0x1p-30);
-    g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
-    g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
+    geo_static(pl, g);
     uint64_t wins = 0, btab_len = 0;
     if (hh[0] != 0 || hh[B] != n) return RHG_EDEVICE;
     for (int j = 0; j < B; ++j) {
         if (hh[j + 1] < hh[j]) return RHG_EDEVICE;
-        g.c[j] = pl.c[j];
-        g.shc[j] = std::sinh(pl.c[j]);
-        g.epc[j] = std::exp(pl.c[j]);
-        g.emc[j] = std::exp(-pl.c[j]);
-        g.ishc[j] = j > 0 ? 1.0 / g.shc[j] : 0.0;
         g.bs[j] = hh[j];
         g.winbase[j] = wins;
         const uint32_t nj = hh[j + 1] - hh[j];
@@ -372,7 +383,6 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         g.bto[j] = (uint32_t)btab_len;
         btab_len += (1ull << bits) + 1;
     }
-    g.c[B] = pl.c[B];
     g.bs[B] = (uint32_t)n;
     g.winbase[B] = wins;
     pl.windows = wins;
@@ -494,7 +504,11 @@ rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
 // ---------------------------------------------------------------------------
 // Graph handles and ABI entry points
 // ---------------------------------------------------------------------------
-static rhg_status request_from_params(const rhg_params *p, Request &rq) {
+double rhgi::expected_degree(uint64_t n, double alpha, double R) {
+    return alpha > 0.5 ? kbar_of_R((double)n, alpha, R) : (double)n;
+}
+
+rhg_status rhgi::request_from_params(const rhg_params *p, Request &rq) {
     if (!p) return RHG_EINVAL;
     rq = Request{};
     rq.mode = SRC_SEED;
@@ -516,7 +530,7 @@ static rhg_status request_from_params(const rhg_params *p, Request &rq) {
 
 namespace rhgi {
 
-static void graph_release(Graph *g) {
+void graph_release(Graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
     auto fr = [&](void *p) {
@@ -524,7 +538,8 @@ static void graph_release(Graph *g) {
         if (g->free_fn) g->free_fn(p, g->alloc_user);
         else (void)hipFree(p);
     };
-    fr(g->edges);
+    if (g->edge_owner) g->edge_owner.reset();  // slice of a shared output pool
+    else fr(g->edges);
     fr(g->d_theta);
     fr(g->d_r);
     fr(g->d_table);

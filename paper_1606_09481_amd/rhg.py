@@ -46,6 +46,14 @@ class rhg_stats(ctypes.Structure):
         return d
 
 
+class rhg_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("batched", ctypes.c_uint64), ("groups", ctypes.c_uint64),
+                ("fallbacks", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def params(n: int, alpha: float = 1.0, kbar: float = 10.0, R: float = 0.0, seed: int = 1,
            precision: int = RHG_FP64, num_bands: int = 0, band_ratio: float = 0.0) -> rhg_params:
     return rhg_params(int(n), float(alpha), float(kbar), float(R), int(seed), int(precision), int(num_bands),
@@ -98,6 +106,7 @@ def load(path: Optional[str] = None):
         "rhg_server_create": (i32, [i32, u64, P(vp)]),
         "rhg_server_submit": (i32, [vp, P(rhg_params), P(u64)]),
         "rhg_server_wait": (i32, [vp, u64, i32, P(vp), P(d)]),
+        "rhg_server_counters": (i32, [vp, P(rhg_server_stats)]),
         "rhg_server_destroy": (None, [vp]),
         "rhg_status_str": (ctypes.c_char_p, [i32]),
         "rhg_version": (ctypes.c_char_p, []),
@@ -302,6 +311,12 @@ def rhg_server_wait(s, ticket: int, timeout_ms: int = -1):
     _check(load().rhg_server_wait(s, int(ticket), int(timeout_ms), ctypes.byref(g), ctypes.byref(lat)),
            "rhg_server_wait")
     return g, lat.value
+
+
+def rhg_server_counters(s) -> dict:
+    out = rhg_server_stats()
+    _check(load().rhg_server_counters(s, ctypes.byref(out)), "rhg_server_counters")
+    return out.as_dict()
 
 
 def rhg_server_destroy(s):

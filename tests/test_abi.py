@@ -78,6 +78,12 @@ def test_null_handles_rejected(lib):
     assert lib.rhg_graph_stats(None, None) == rhg.RHG_EINVAL
     lib.rhg_graph_free(None)
     lib.rhg_ctx_destroy(None)
+    t = ctypes.c_uint64()
+    assert lib.rhg_server_submit(None, ctypes.byref(p), ctypes.byref(t)) == rhg.RHG_EINVAL
+    assert lib.rhg_server_wait(None, 1, 0, ctypes.byref(g), None) == rhg.RHG_EINVAL
+    assert lib.rhg_server_counters(None, None) == rhg.RHG_EINVAL
+    assert lib.rhg_server_create(0, 0, ctypes.byref(g)) == rhg.RHG_EINVAL  # zero budget
+    lib.rhg_server_destroy(None)
 
 
 def test_product_has_no_oracle_dependency():
