@@ -10,8 +10,10 @@ preallocated device buffer (rhg_count + rhg_emit).  The FP64 form gives
 reported beside it (its edge list is checked byte-identical).
 
 Also reported: per-phase device times (HIP events on the library stream),
-the roofline of the dominant kernel, and the CPU oracle on a bounded sample
-of the same workload (cpu_baseline).
+the roofline of the dominant kernel, the CPU oracle on a bounded sample of
+the same workload (cpu_baseline), and the request server on a stream of
+2000 mixed requests (serving): closed-loop saturation throughput X, then
+Poisson arrivals at 0.7 X with p50/p99 latency and aggregate edges/s.
 """
 from __future__ import annotations
 
@@ -96,6 +98,89 @@ def run_gpu(args):
     return res
 
 
+def serving_requests(rhg, count, seed):
+    """The serving mix: n log-uniform in [1e3, 2e6], alpha uniform in
+    [0.55, 1.5], kbar uniform integer in 6..64 (combinations whose average
+    degree the model cannot reach are drawn again), request i seeded base+i."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        n = int(round(math.exp(rng.uniform(math.log(1e3), math.log(2e6)))))
+        alpha = float(rng.uniform(0.55, 1.5))
+        kbar = float(rng.integers(6, 65))
+        try:
+            rhg.rhg_target_radius(n, alpha, kbar)
+        except rhg.RhgError:
+            continue
+        out.append(rhg.params(n, alpha, kbar=kbar, seed=1000 + len(out)))
+    return out
+
+
+def _serve(rhg, srv, reqs, arrivals):
+    """Submits reqs[i] at arrivals[i] seconds (None: all at once) from a
+    submitter thread; collects in order.  Returns (wall s, latencies ms, edges)."""
+    import queue
+    import threading
+    q = queue.Queue()
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, p in enumerate(reqs):
+            if arrivals is not None:
+                d = t_start + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+            q.put(rhg.rhg_server_submit(srv, p))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, edges = [], 0
+    for _ in reqs:
+        g, ms = rhg.rhg_server_wait(srv, q.get())
+        edges += rhg.rhg_graph_num_edges(g)
+        rhg.rhg_graph_free(g)
+        lat.append(ms)
+    th.join()
+    return time.perf_counter() - t_start, lat, edges
+
+
+def run_serving(args):
+    import numpy as np
+    from paper_1606_09481_amd import rhg
+    rhg.load()
+    reqs = serving_requests(rhg, args.serve_requests, args.seed)
+    small = np.array([p.n <= 16384 for p in reqs])
+    srv = rhg.rhg_server_create(0, args.serve_budget_gb << 30)
+    try:
+        _serve(rhg, srv, reqs[:100], None)  # warm-up: lane buffers, code objects
+        T_sat, lat_sat, edges = _serve(rhg, srv, reqs, None)
+        X = len(reqs) / T_sat
+        lam = 0.7 * X
+        rng = np.random.default_rng(args.seed + 7)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        T, lat, edges2 = _serve(rhg, srv, reqs, arrivals)
+        cnt = rhg.rhg_server_counters(srv)
+    finally:
+        rhg.rhg_server_destroy(srv)
+    lat = np.array(lat)
+    pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None
+    print("[bench] serving: saturation %.1f req/s (%.3g edges/s), open loop at %.1f req/s: p50 %.3f ms p99 %.3f ms"
+          % (X, edges / T_sat, lam, pct(lat, 50), pct(lat, 99)), file=sys.stderr, flush=True)
+    return {
+        "requests": len(reqs), "edges": int(edges), "budget_bytes": args.serve_budget_gb << 30,
+        "mix": "n log-uniform [1e3, 2e6], alpha U[0.55, 1.5], kbar U{6..64}, request i seed 1000+i, FP64",
+        "saturation_req_per_s": X, "saturation_edges_per_s": edges / T_sat,
+        "arrival_rate_req_per_s": lam, "arrivals": "Poisson, seed %d" % (args.seed + 7),
+        "edges_per_s": edges2 / T, "wall_s": T,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(lat.mean()), "max": float(lat.max()),
+                       "small_p50": pct(lat[small], 50), "small_p99": pct(lat[small], 99),
+                       "large_p50": pct(lat[~small], 50), "large_p99": pct(lat[~small], 99)},
+        "latency_definition": "submit (at arrival) to results host-visible after the device finished",
+        "small_fraction": float(small.mean()), "counters": cnt,
+    }
+
+
 def cpu_baseline(args, m_full):
     """The oracle as it stands on the host cores: sample + table + slab sort of
     all n points timed in full; the band sweep on the first `frac` of the
@@ -135,6 +220,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-frac", type=float, default=0.1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-budget-gb", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this generator runs on one GPU; multi-GPU sharding is not built (see DESIGN.md)",
@@ -167,6 +255,8 @@ def main():
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
         "roofline": roof,
     }
+    if not args.no_serve:
+        line["serving"] = run_serving(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args, f64["m"])
     print(json.dumps(line), flush=True)

@@ -78,8 +78,9 @@ void query_emit(const QueryArgs &a, int fp32, hipStream_t st);
 // One-launch generation of small requests: one workgroup per descriptor.
 // The host fills src, the static geometry (n, B, R, K, Kw, FP32 thresholds,
 // slab constants), fp32, key_bits and the scratch pointers with their
-// capacities; the device fills the rest.  status: 0 done, 1 scratch too
-// small (rerun on the multi-launch path), 2 output pool full.
+// capacities (stats zeroed); the device writes one SmallResult per request.
+// status: 0 done, 1 scratch too small (rerun on the multi-launch path),
+// 2 output pool full (same).
 constexpr uint32_t SMALL_N = 16384;
 struct SmallDesc {
     rhgd::Source src;
@@ -98,11 +99,13 @@ struct SmallDesc {
     uint64_t *ueoff;
     unsigned long long *bits;
     uint64_t unit_cap;
-    unsigned long long *stats;  // [rechecks, disagreements]
-    uint64_t m, candidates, windows, out_off, rechecks;
-    int status;  // -1 pending, 0 done, 1 scratch too small, 2 output pool full, 3 invalid
+    unsigned long long *stats;  // [rechecks, disagreements], zero at launch
 };
-void small_group(SmallDesc *descs, int count, int2 *pool, unsigned long long *pool_used, uint64_t pool_cap,
-                 hipStream_t st);
+struct SmallResult {
+    uint64_t m, candidates, windows, out_off, rechecks;
+    int status;
+};
+void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
+                 unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st);
 
 }  // namespace rhgk

@@ -310,6 +310,7 @@ int key_bits_for(int B) { return QBITS + std::max(1, ceil_log2((uint64_t)B)); }
 
 rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();  // launch errors checked below are this call's own
     const hipStream_t st = c->stream;
     const uint64_t n = pl.n;
     const int B = pl.B;
@@ -475,6 +476,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
 rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
     if (pl.generation != c->generation) return RHG_EINVAL;  // context reused since the count
     RHG_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();
     const hipStream_t st = c->stream;
     pl.qa.out = out;
     pl.qa.out_capacity = pl.m;

@@ -140,15 +140,16 @@ __device__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t
     }
 }
 
-__global__ __launch_bounds__(SM_THREADS) void k_small(SmallDesc *descs, int2 *pool, unsigned long long *pool_used,
-                                                      uint64_t pool_cap) {
+__global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, SmallResult *results, int2 *pool,
+                                                      unsigned long long *pool_used, uint64_t pool_cap) {
     __shared__ QueryArgs sA;
     __shared__ PhaseSmem P;
     __shared__ ScanSmem SS;
     __shared__ uint32_t s_bs[MAX_BANDS + 1];
     __shared__ int s_flag;
 
-    SmallDesc &D = descs[blockIdx.x];
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
@@ -227,12 +228,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(SmallDesc *descs, int2 *po
         sA.geo.hsc = D.hsc;
         sA.geo.f32 = D.f32;
         sA.geo.btab = D.btab;
-        D.windows = wins;
+        Z.windows = wins;
         if (wins > D.win_cap || btl > D.btab_cap) s_flag = 1;
     }
     __syncthreads();
     if (s_flag) {
-        if (t == 0) D.status = 1;
+        if (t == 0) Z.status = 1;
         return;
     }
     const Geo &g = sA.geo;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(SmallDesc *descs, int2 *po
     blk_scan_array(D.nunits, D.uoff, nb, SS);
     const uint64_t U = D.uoff[nb];
     if (U > D.unit_cap) {
-        if (t == 0) D.status = 1;
+        if (t == 0) Z.status = 1;
         return;
     }
     for (uint32_t u = t; u < U; u += SM_THREADS) {
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(SmallDesc *descs, int2 *po
         sA.out_capacity = 0;
         sA.stats = D.stats;
         sA.exhaustive = 0;
-        D.candidates = D.boff[nb];
+        Z.candidates = D.boff[nb];
     }
     __syncthreads();
 
@@ -337,28 +338,28 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(SmallDesc *descs, int2 *po
             }
             cur = prev;
         }
-        D.m = m;
-        D.out_off = off;
-        D.rechecks = atomicAdd(&D.stats[0], 0ull);
+        Z.m = m;
+        Z.out_off = off;
+        Z.rechecks = atomicAdd(&D.stats[0], 0ull);
         s_flag = fits ? 0 : 1;
         sA.out = pool + off;
         sA.out_capacity = m;
     }
     __syncthreads();
     if (s_flag) {
-        if (t == 0) D.status = 2;
+        if (t == 0) Z.status = 2;
         return;
     }
 
     // ---- a7: emit
     for (uint64_t u = w; u < U; u += SM_WAVES) emit_unit<false>(sA, u, lane, P.emit[w]);
-    if (t == 0) D.status = 0;
+    if (t == 0) Z.status = 0;
 }
 
-void small_group(SmallDesc *descs, int count, int2 *pool, unsigned long long *pool_used, uint64_t pool_cap,
-                 hipStream_t st) {
+void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
+                 unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st) {
     if (count > 0)
-        hipLaunchKernelGGL(k_small, dim3(count), dim3(SM_THREADS), 0, st, descs, pool, pool_used, pool_cap);
+        hipLaunchKernelGGL(k_small, dim3(count), dim3(SM_THREADS), 0, st, descs, results, pool, pool_used, pool_cap);
 }
 
 }  // namespace rhgk
