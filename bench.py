@@ -187,7 +187,7 @@ def cpu_baseline(args, m_full):
     queries (i.i.d. points: a uniform sample), scaled by 1/frac."""
     import oracle
     frac = args.cpu_frac
-    threads = os.cpu_count() or 1
+    threads = oracle.default_threads()
     t0 = time.perf_counter()
     R = oracle.target_radius(args.n, args.alpha, args.kbar)
     th, r = oracle.sample(args.n, args.alpha, R, args.seed)
@@ -221,6 +221,7 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=0.1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving stream (prints its JSON)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
     args = ap.parse_args()
@@ -229,6 +230,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.serve_only:
+        print(json.dumps({"serving": run_serving(args)}), flush=True)
+        return
     res = run_gpu(args)
     f64, f32 = res["fp64"], res["fp32_recheck"]
     n = args.n

@@ -60,6 +60,8 @@ def lib():
         L.orc_splitmix64.argtypes = [u64, u64]
         L.orc_sample.restype = None
         L.orc_sample.argtypes = [u64, d, d, u64, vp, vp]
+        L.orc_sample_range.restype = None
+        L.orc_sample_range.argtypes = [u64, u64, d, d, u64, vp, vp]
         L.orc_table.restype = None
         L.orc_table.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_coshdist.restype = d
@@ -81,6 +83,12 @@ def lib():
         L.orc_free.argtypes = [vp]
         _lib = L
     return _lib
+
+
+def default_threads() -> int:
+    """Host threads for the threaded oracle routines: the machine's cores, at
+    most 16 (the CPU share one GPU job may use on a shared host)."""
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def _ptr(a: np.ndarray):
@@ -127,20 +135,49 @@ def splitmix64(seed: int, k: int) -> int:
     return int(lib().orc_splitmix64(int(seed) & (2**64 - 1), int(k)))
 
 
-def sample(n: int, alpha: float, R: float, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+_CHUNK = 1 << 20
+
+
+def _chunks(n: int, threads: int):
+    """Splits [0, n) into ranges for host threads (each point is independent)."""
+    if threads <= 0:
+        threads = default_threads()
+    if n <= _CHUNK or threads == 1:
+        return [(0, n)], 1
+    return [(a, min(n, a + _CHUNK)) for a in range(0, n, _CHUNK)], threads
+
+
+def _run(jobs, threads):
+    if threads == 1:
+        for j in jobs:
+            j()
+        return
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda j: j(), jobs))
+
+
+def sample(n: int, alpha: float, R: float, seed: int, threads: int = 0) -> Tuple[np.ndarray, np.ndarray]:
     theta = np.empty(n, dtype=np.float64)
     r = np.empty(n, dtype=np.float64)
-    lib().orc_sample(int(n), float(alpha), float(R), int(seed), _ptr(theta), _ptr(r))
+    L = lib()
+    ranges, threads = _chunks(n, threads)
+    _run([lambda a=a, b=b: L.orc_sample_range(a, b, float(alpha), float(R), int(seed), _ptr(theta), _ptr(r))
+          for a, b in ranges], threads)
     return theta, r
 
 
-def table(theta: np.ndarray, r: np.ndarray) -> np.ndarray:
+def table(theta: np.ndarray, r: np.ndarray, threads: int = 0) -> np.ndarray:
     """(5, n) array: exp(r), exp(-r), sinh r, sin(theta/2), cos(theta/2)."""
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     r = np.ascontiguousarray(r, dtype=np.float64)
     n = len(theta)
     t = np.empty((5, n), dtype=np.float64)
-    lib().orc_table(n, _ptr(theta), _ptr(r), _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), _ptr(t[4]))
+    L = lib()
+    ranges, threads = _chunks(n, threads)
+    _run([lambda a=a, b=b: L.orc_table(b - a, _ptr(theta[a:]), _ptr(r[a:]), _ptr(t[0, a:]), _ptr(t[1, a:]),
+                                       _ptr(t[2, a:]), _ptr(t[3, a:]), _ptr(t[4, a:]))
+          for a, b in ranges], threads)
     return t
 
 
@@ -180,7 +217,7 @@ def brute_rows(tab: np.ndarray, K: float, queries, threads: int = 0) -> np.ndarr
     tab = np.ascontiguousarray(tab, dtype=np.float64)
     q = np.ascontiguousarray(queries, dtype=np.int64)
     if threads <= 0:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     p = ctypes.c_void_p()
     m = lib().orc_brute_rows(tab.shape[1], _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]), _ptr(tab[4]),
                              float(K), _ptr(q), len(q), int(threads), ctypes.byref(p))
@@ -207,7 +244,7 @@ def band_sweep(theta: np.ndarray, r: np.ndarray, tab: np.ndarray, R: float, K: f
     if q1 is None:
         q1 = n
     if threads <= 0:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     ptr = ctypes.c_void_p()
     cand = ctypes.c_uint64()
     m = lib().orc_band_sweep(n, _ptr(theta), _ptr(r), _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]),

@@ -149,15 +149,19 @@ static double orc_unit(uint64_t x) { return (double)(x >> 11) * (1.0 / 900719925
  * radius: inverse of F(r) = (cosh(alpha r) - 1)/(cosh(alpha R) - 1)
  *       = sinh^2(alpha r / 2) / sinh^2(alpha R / 2),
  *   i.e. r = 2 asinh( sqrt(u) sinh(alpha R / 2) ) / alpha, clamped to [0, R]. */
-void orc_sample(uint64_t n, double alpha, double R, uint64_t seed, double *theta, double *r) {
+void orc_sample_range(uint64_t i0, uint64_t i1, double alpha, double R, uint64_t seed, double *theta, double *r) {
     double sR = sinh(alpha * R / 2.0);
-    for (uint64_t i = 0; i < n; ++i) {
+    for (uint64_t i = i0; i < i1; ++i) {
         double u1 = orc_unit(orc_splitmix64(seed, 2 * i));
         double u2 = orc_unit(orc_splitmix64(seed, 2 * i + 1));
         theta[i] = u1 * ORC_TWO_PI;
         double ri = 2.0 * asinh(sqrt(u2) * sR) / alpha;
         r[i] = ri > R ? R : ri;
     }
+}
+
+void orc_sample(uint64_t n, double alpha, double R, uint64_t seed, double *theta, double *r) {
+    orc_sample_range(0, n, alpha, R, seed, theta, r);
 }
 
 /* ------------------------------------------------------------------------- */

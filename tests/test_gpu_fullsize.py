@@ -1,0 +1,134 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark
+times (rhg_count + rhg_emit into one preallocated device buffer).
+
+Workloads: n = 10^7, alpha = 0.75, kbar = 100 (about 5.0e8 edges), and the
+exponent sweep n = 4*10^6, kbar = 64, alpha in {0.55, 1.0, 1.5} (alpha = 0.55
+has hubs adjacent to about 10^6 points), both precision forms.
+
+The oracle cannot list 10^8..10^9 edges pair by pair, so it answers for
+sampled vertices: every neighbour of 96 random vertices, of the 16 innermost
+points (the hubs, whose windows span whole slabs) and of the 16 outermost
+ones, by the all-pairs definition on those rows.  Checked:
+  * table mode (the oracle's own table handed to the device): the edges
+    incident to the sampled vertices are exactly the oracle's;
+  * seeded mode (the device samples and builds its table): the same, except
+    pairs within the table rounding of the threshold (reported, bounded);
+  * the whole output: lo < hi, indices in range, FP32+recheck bytes equal to
+    FP64 bytes, m within 5% of n kbar / 2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import parity
+from paper_1606_09481_amd import rhg
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(10_000_000, 0.75, 100.0), (4_000_000, 0.55, 64.0), (4_000_000, 1.0, 64.0), (4_000_000, 1.5, 64.0)]
+def _oracle_case(orc, n, alpha, kbar):
+    R = orc.target_radius(n, alpha, kbar)
+    th, r = orc.sample(n, alpha, R, 1)
+    t = orc.table(th, r)
+    rng = np.random.default_rng(n + int(1000 * alpha))
+    order = np.argsort(r, kind="stable")
+    rows = np.unique(np.concatenate([rng.choice(n, 96, replace=False), order[:16], order[-16:]]))
+    ref = orc.brute_rows(t, math.cosh(R), rows)
+    ref = np.unique(np.sort(ref.reshape(-1, 2), axis=1).astype(np.int64) @ np.array([1 << 32, 1], np.int64))
+    return R, th, r, t, rows, ref
+
+
+@pytest.fixture(scope="module")
+def torch_ctx():
+    import torch
+    rhg.load()
+    torch.cuda.set_device(0)
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    yield c
+    rhg.rhg_ctx_destroy(c)
+
+
+def _incident_device(out, m, rows, n):
+    """Canonical keys of the device edges touching `rows`, plus whole-output checks."""
+    import torch
+    flag = torch.zeros(n, dtype=torch.bool, device=out.device)
+    flag[torch.as_tensor(rows, device=out.device)] = True
+    sel = []
+    chunk = 1 << 25
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        e = out[2 * a:2 * b].view(-1, 2).long()
+        assert bool((e[:, 0] < e[:, 1]).all()), "lo < hi"
+        assert int(e[:, 0].min()) >= 0 and int(e[:, 1].max()) < n, "indices in range"
+        mk = flag[e[:, 0]] | flag[e[:, 1]]
+        sel.append(e[mk].cpu())
+    e = torch.cat(sel).numpy()
+    k = (e[:, 0] << 32) | e[:, 1]
+    ks = np.sort(k)
+    assert np.all(ks[1:] != ks[:-1]), "each edge once"
+    return ks
+
+
+class _Dev:
+    def __init__(self, ptr, count):
+        self.__cuda_array_interface__ = {"shape": (count,), "typestr": "<i4", "data": (int(ptr), False),
+                                         "version": 3}
+
+
+def _device_view(ptr, count):
+    """Zero-copy int32 tensor over library-owned device memory (valid while the graph lives)."""
+    import torch
+    return torch.as_tensor(_Dev(ptr, count), device="cuda")
+
+
+def _count_emit(ctx, p):
+    import torch
+    plan, m = rhg.rhg_count(ctx, p)
+    out = torch.empty(2 * m + 2, dtype=torch.int32, device="cuda")
+    rhg.rhg_emit(ctx, plan, out, m + 1)
+    torch.cuda.synchronize()
+    st = rhg.rhg_graph_stats(plan)
+    R = rhg.rhg_graph_radius(plan)
+    rhg.rhg_graph_free(plan)
+    return out, m, st, R
+
+
+@pytest.mark.parametrize("n,alpha,kbar", CASES)
+def test_fullsize(torch_ctx, orc, n, alpha, kbar):
+    import torch
+    print("case", n, alpha, kbar, flush=True)
+    R, th, r, t, rows, ref = _oracle_case(orc, n, alpha, kbar)
+    K = math.cosh(R)
+
+    # table mode: identical table bits on both sides -> identical incident edges
+    for prec in (rhg.RHG_FP64, rhg.RHG_FP32_RECHECK):
+        g = rhg.rhg_generate_from_table(torch_ctx, th, r, t, R, prec)
+        try:
+            m = rhg.rhg_graph_num_edges(g)
+            got = _incident_device(_device_view(rhg.rhg_graph_edges_device(g), 2 * m), m, rows, n)
+        finally:
+            rhg.rhg_graph_free(g)
+        assert len(got) == len(ref) and np.array_equal(got, ref), \
+            "table mode, prec %d: %d incident edges vs %d in the oracle" % (prec, len(got), len(ref))
+    print("table mode exact:", len(ref), "incident edges of", len(rows), "vertices", flush=True)
+
+    # seeded, as the benchmark runs it
+    out64, m64, st64, R64 = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1))
+    assert R64 == R
+    assert abs(m64 - n * kbar / 2) <= 0.05 * n * kbar / 2
+    got = _incident_device(out64, m64, rows, n)
+    diff = np.setxor1d(got, ref)  # only pairs within the table rounding of K may differ
+    if len(diff):
+        u = (diff >> 32).astype(np.int64)
+        v = (diff & 0xffffffff).astype(np.int64)
+        V, bound = parity.ambiguity_bound(t, u, v)
+        assert not (np.abs(V - K) > bound).any(), "pairs far from the threshold decided differently"
+        assert len(diff) <= 16
+    print("seeded: ambiguous pairs", len(diff), "of", len(ref), flush=True)
+    out32, m32, st32, _ = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1,
+                                                            precision=rhg.RHG_FP32_RECHECK))
+    assert m32 == m64
+    assert bool(torch.equal(out32[:2 * m64], out64[:2 * m64])), "FP32+recheck bytes differ from FP64"
+    assert st32["candidates"] == st64["candidates"]
+    print("rechecks", st32["rechecks"], "of", st32["candidates"], "candidates", flush=True)
