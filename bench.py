@@ -87,6 +87,7 @@ def run_gpu(args):
         T = sum(times) / len(times)
         res[name] = {
             "m": m, "R": R, "s_per_step": T, "edges_per_s": m / T,
+            "count_kernel_ms": sum(s["count_kernel_ms"] for s in stats) / len(stats),
             "phases_ms": {"keys": avg(0), "sort": avg(1), "table_index": avg(2), "plan_units": avg(3),
                           "count": avg(4), "edge_scan": avg(5), "emit": avg(6), "device_total": avg(7)},
             "candidates": stats[0]["candidates"], "windows": stats[0]["windows"],
@@ -96,6 +97,45 @@ def run_gpu(args):
     rhg.rhg_ctx_destroy(ctx)
     del out, ref_edges
     return res
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_traffic_n1e7_a075_k100.md")
+KERNEL_SOURCES = ["query_dev.h", "query.hip", "rhg_device.h", "rhg_kernels.h"]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of kernel `key` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel sources
+    no longer hash to the ones the counters were taken with."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().split("\n")
+    except OSError:
+        return None, None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1606_09481_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    want = [l.split()[1] for l in lines if l.strip().startswith("sources_sha256")]
+    if not want or want[0] != h.hexdigest():
+        return None, "counters taken with other kernel sources"
+    for l in lines:
+        t = l.split()
+        if len(t) == 3 and t[0] == "traffic" and t[1] == key:
+            return int(t[2]), os.path.relpath(TRAFFIC_FILE, ROOT)
+    return None, None
+
+
+def copy_calibration(mib):
+    """Three device-to-device copies of mib MiB: each reads and writes exactly
+    mib MiB, the reference for FETCH_SIZE / WRITE_SIZE per dispatch."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("[bench] copy calibration: 3 x %d MiB device copies" % mib, file=sys.stderr, flush=True)
 
 
 def serving_requests(rhg, count, seed):
@@ -222,6 +262,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving stream (prints its JSON)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the steps, copy a MIB-MiB device buffer 3 times (the known-size kernel that "
+                         "scales HBM byte counters under rocprofv3 --pmc)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
     args = ap.parse_args()
@@ -234,17 +277,22 @@ def main():
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return
     res = run_gpu(args)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     f64, f32 = res["fp64"], res["fp32_recheck"]
     n = args.n
     cnt_b, emit_b = kernel_bytes(n, f64["windows"], 0, f64["m"])
     ph = f64["phases_ms"]
-    if ph["emit"] >= ph["count"]:
-        kname, kbytes, kms = "k_query<emit,fp64>", emit_b, ph["emit"]
+    if ph["emit"] >= f64["count_kernel_ms"]:
+        kname, kkey, kbytes, kms = "k_emit<false>", "k_emit", emit_b, ph["emit"]
     else:
-        kname, kbytes, kms = "k_query<count,fp64>", cnt_b, ph["count"]
+        kname, kkey, kbytes, kms = "k_count<0,false>", "k_count", cnt_b, f64["count_kernel_ms"]
     achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic(kkey) if (n, args.alpha, args.kbar, args.seed) == (
+        10_000_000, 0.75, 100.0, 1) else (None, None)
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": kbytes, "avg_ms": kms}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": kbytes, "avg_ms": kms,
+            "traffic_source": traffic_src, "count_kernel_ms": f64["count_kernel_ms"]}
     line = {
         "metric": METRIC, "value": f64["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * f64["s_per_step"], "higher_is_better": True,

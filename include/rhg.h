@@ -94,7 +94,9 @@ typedef struct rhg_server rhg_server;
  *               3 slab index + window plan + unit scans, 4 count, 5 edge scan,
  *               6 emit, 7 sum of 0-6 (host synchronisation gaps excluded)
  *   bytes_moved algorithmic HBM bytes of phases 1-6 (reads + writes the
- *               method needs), for roofline reporting */
+ *               method needs), for roofline reporting
+ *   count_kernel_ms  device time of the count kernel alone (ms[4] without the
+ *               unit bookkeeping and ordering launches) */
 typedef struct {
     uint64_t edges;
     uint64_t candidates;
@@ -103,6 +105,7 @@ typedef struct {
     uint64_t disagreements; /* FP32 decisions differing from FP64 (exhaustive option only; must be 0) */
     double ms[8];
     uint64_t bytes_moved;
+    double count_kernel_ms;
 } rhg_stats;
 
 /* ---- context ------------------------------------------------------------ */

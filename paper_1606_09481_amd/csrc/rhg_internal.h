@@ -21,7 +21,7 @@ enum Slot {
 };
 
 enum Ev { EV_KEYS0, EV_KEYS1, EV_SORT0, EV_SORT1, EV_TABLE1, EV_PLAN0, EV_PLAN1, EV_COUNT0, EV_COUNT1, EV_SCAN1,
-          EV_EMIT0, EV_EMIT1, EV_COUNT_ };
+          EV_EMIT0, EV_EMIT1, EV_QCOUNT0, EV_COUNT_ };
 
 struct SlotBuf {
     void *ptr = nullptr;
@@ -74,6 +74,7 @@ struct Plan {
     uint64_t generation = 0;
     bool emitted = false;
     double ms[8] = {};
+    double count_kernel_ms = 0;  // the count kernel alone (ms[4] also holds unit bookkeeping and order)
 };
 
 struct Graph {

@@ -459,6 +459,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.unit_order = nullptr;
     rhgk::unit_order(qa, ukey, uorder, ukey2, uorder2, usort, st);
     qa.unit_order = uorder;
+    RHG_HIP(hipEventRecord(c->ev[EV_QCOUNT0], st));
     rhgk::query_count(qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
     rhgk::scan_u32(uedges, ueoff, U, scan2, st);
@@ -497,6 +498,9 @@ rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
         tot += t;
     }
     pl.ms[7] = tot;
+    float tq = 0;
+    (void)hipEventElapsedTime(&tq, c->ev[EV_QCOUNT0], c->ev[EV_COUNT1]);
+    pl.count_kernel_ms = tq;
     pl.emitted = true;
     return RHG_OK;
 }
@@ -761,6 +765,7 @@ extern "C" rhg_status rhg_graph_stats(const rhg_graph *gr, rhg_stats *st) {
     st->disagreements = g->pl.disagreements;
     for (int k = 0; k < 8; ++k) st->ms[k] = g->pl.ms[k];
     st->bytes_moved = algorithmic_bytes(g->pl);
+    st->count_kernel_ms = g->pl.count_kernel_ms;
     return RHG_OK;
 }
 

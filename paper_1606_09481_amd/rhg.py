@@ -38,7 +38,8 @@ class rhg_params(ctypes.Structure):
 class rhg_stats(ctypes.Structure):
     _fields_ = [("edges", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
                 ("windows", ctypes.c_uint64), ("disagreements", ctypes.c_uint64),
-                ("ms", ctypes.c_double * 8), ("bytes_moved", ctypes.c_uint64)]
+                ("ms", ctypes.c_double * 8), ("bytes_moved", ctypes.c_uint64),
+                ("count_kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms"}
