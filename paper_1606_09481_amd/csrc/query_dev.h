@@ -231,9 +231,22 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
     }
 }
 
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    return ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32) | uniform_u32((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+}
+
 // Per-unit setup shared by the count and emit passes: the unit's batch and
-// flattened range [r0, r1), the lane's query, and the first slab whose
-// segment reaches past r0 (from the batch's per-slab offsets).
+// flattened range [r0, r1), the lane's query, the first slab whose segment
+// reaches past r0, and the slab segments the unit meets: bit k of segmask is
+// slab jmin + k, whose segment of the batch's flattened candidate list is
+// [rlo, rhi) of lane k (the batch's per-slab offsets).
 struct UnitSetup {
     uint32_t b;
     uint64_t r0, r1;
@@ -241,6 +254,9 @@ struct UnitSetup {
     bool valid;
     int iv, jstart;
     uint64_t pos;  // flattened offset of slab jstart's segment
+    int jmin;
+    uint32_t segmask;
+    uint64_t rlo, rhi;
 };
 
 __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
@@ -254,13 +270,18 @@ __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t uni
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
     u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
-    const int jmin = (int)(g.keys[u.b * BATCH] >> QBITS);
-    // segments of slabs jmin..B-1 end at row[j+1]; skip those ending at or before r0
+    const int jmin = (int)uniform_u32(g.keys[u.b * BATCH] >> QBITS);
+    // segments of slabs jmin..B-1 end at row[j+1] (row[jmin] = 0)
     const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
     const int k = jmin + lane;
-    const bool done = k < g.B && row[k + 1] <= u.r0;
+    u.rhi = (k < g.B) ? row[k + 1] : bc;
+    u.rlo = __shfl_up(u.rhi, 1, 64);
+    if (lane == 0) u.rlo = 0;
+    const bool done = k < g.B && u.rhi <= u.r0;
     u.jstart = jmin + __popcll(__ballot(done));
     u.pos = (u.jstart < g.B) ? row[u.jstart] : bc;
+    u.jmin = jmin;
+    u.segmask = (uint32_t)__ballot(k < g.B && u.rhi > u.rlo && u.rhi > u.r0 && u.rlo < u.r1);
     return u;
 }
 
@@ -274,6 +295,49 @@ __device__ __forceinline__ void slab_windows(const Geo &g, const QueryArgs &A, c
         st = x.x;
         cnt = x.y;
     }
+    const uint32_t incl = wave_incl_scan_u32(cnt);
+    tot = wave_bcast_u32(incl, 63);
+    excl = incl - cnt;
+}
+
+// Windows of the first SEG_PRE segments of a unit, loaded together at the
+// unit's start (one memory round trip, before the pass issues any store) and
+// kept in LDS; later segments load their windows when reached.
+constexpr int SEG_PRE = 3;
+
+__device__ __forceinline__ void prefetch_windows(const QueryArgs &A, const UnitSetup &u, int lane,
+                                                 uint2 (*wpre)[64]) {
+    const Geo &g = A.geo;
+    uint32_t mk = u.segmask;
+    uint2 x[SEG_PRE];
+#pragma unroll
+    for (int s = 0; s < SEG_PRE; ++s) {
+        const bool any = mk != 0u;
+        const int j = u.jmin + (any ? __builtin_ctz(mk) : 0);
+        mk &= mk - 1u;
+        const bool take = any && u.valid && j >= u.iv;
+        const uint64_t at = take ? g.winbase[j] + u.v : 0ull;
+        const uint2 y = A.win[at];
+        x[s] = take ? y : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int s = 0; s < SEG_PRE; ++s) wpre[s][lane] = x[s];
+}
+
+// Lane's window in the seg-th segment of the unit (slab j) and its scan.
+__device__ __forceinline__ void segment_windows(const QueryArgs &A, const UnitSetup &u, int seg, int j, int lane,
+                                                uint2 (*wpre)[64], uint32_t &st, uint32_t &cnt, uint32_t &excl,
+                                                uint32_t &tot) {
+    const Geo &g = A.geo;
+    uint2 x;
+    if (seg < SEG_PRE) {
+        x = wpre[seg][lane];
+    } else {
+        x = make_uint2(0u, 0u);
+        if (u.valid && j >= u.iv) x = A.win[g.winbase[j] + u.v];
+    }
+    st = x.x;
+    cnt = x.y;
     const uint32_t incl = wave_incl_scan_u32(cnt);
     tot = wave_bcast_u32(incl, 63);
     excl = incl - cnt;
@@ -346,6 +410,7 @@ struct CountSmem {
     double qd[5][64];   // per rank: query operands
     float qf[3][64];
     unsigned long long bits[BITW];
+    uint2 wpre[SEG_PRE][64];
 };
 
 template <int FP32, bool WIDE>
@@ -374,12 +439,18 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    uint64_t pos = u.pos;  // flattened offset of slab j's segment within the batch
+    prefetch_windows(A, u, lane, S.wpre);
     uint32_t word = 0;     // next free bitmap word
     uint32_t found = 0, rechecks = 0, disagree = 0;
-    for (int j = u.jstart; j < g.B && pos < u.r1; ++j) {
+    uint32_t segs = u.segmask;
+    for (int seg = 0; segs != 0u; ++seg) {
+        const int bit = __builtin_ctz(segs);
+        segs &= segs - 1u;
+        const int j = u.jmin + bit;
+        const uint64_t pos = lane_u64(u.rlo, bit);  // flattened offset of slab j's segment within the batch
         uint32_t st, cnt, excl, tot;
-        slab_windows(g, A, u, j, st, cnt, excl, tot);
+        wave_lds_sync();
+        segment_windows(A, u, seg, j, lane, S.wpre, st, cnt, excl, tot);
         const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
         const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
         const bool ne = cnt != 0u;
@@ -445,7 +516,6 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
             }
             word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
         }
-        pos += tot;
     }
     wave_lds_sync();
     for (uint32_t k = lane; k < word; k += 64) A.bits[unit * BITW + k] = S.bits[k];
@@ -460,81 +530,144 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
 // Emit pass: walk the unit exactly as the count pass did, take the decisions
 // from its bitmap, and write (min, max) original-index pairs, compacted per
 // 64-candidate round, at the unit's offset in the edge list.
+//
+// The walk is software-pipelined by one step: the index gathers of step k+1
+// are issued before the stores of step k.  Loads and stores share one
+// completion counter on this architecture and complete in order, so waiting
+// for a step's gathers never waits for the previous step's write acks.  For
+// the compiler to count the stores statically they must not sit behind
+// exec-skipping branches: every lane stores, through a buffer resource that
+// spans exactly this unit's output slice, and lanes without an edge give an
+// offset outside it, which the hardware range check drops.  The same check
+// keeps every store inside the unit's slice and the caller's capacity.
 // Per-wavefront LDS of the emit pass.
 struct EmitSmem {
     uint32_t pb[64];
     uint32_t flag[64 * VT_EMIT];
     uint32_t qi[64];
-    unsigned long long bits[BITW];
+    unsigned long long bits[BITW + VT_EMIT];
+    uint2 wpre[SEG_PRE][64];
+};
+
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int BUFFER_WORD3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
+constexpr uint32_t NO_STORE = 0x80000000u; // offset outside every unit's slice
+constexpr int STORE_NT = 2;                 // non-temporal: edges are not read again by this pass
+
+struct EmitStep {
+    uint32_t wi[VT_EMIT];   // gathered original index of the candidate (in flight until stored)
+    uint32_t qi[VT_EMIT];   // original index of the query
+    uint32_t off[VT_EMIT];  // byte offset in the unit's slice, or NO_STORE
+    bool valid;
+};
+
+// Walk state of one unit: the segments left, the current one and the position in it.
+struct EmitWalk {
+    uint32_t segs;
+    int seg;
+    uint32_t t0, e, base, word, be, nj, excl, out_rel;
+    bool ne, in_seg;
 };
 
 template <bool WIDE>
-__device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int lane, EmitSmem &S) {
+__device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup &u, uint32_t myqi, uint32_t todo,
+                                             int lane, uint64_t le, uint64_t lt, EmitSmem &S, EmitWalk &w,
+                                             EmitStep &s) {
     constexpr int VT = VT_EMIT;
     const Geo &g = A.geo;
-    const uint32_t todo = A.unit_edges[unit];
+    s.valid = false;
+    while (!w.in_seg) {
+        if (w.segs == 0u || w.out_rel >= todo) return;
+        const int bit = __builtin_ctz(w.segs);
+        w.segs &= w.segs - 1u;
+        const int j = u.jmin + bit;
+        const uint64_t pos = lane_u64(u.rlo, bit);
+        uint32_t st, cnt, tot;
+        wave_lds_sync();
+        segment_windows(A, u, w.seg, j, lane, S.wpre, st, cnt, w.excl, tot);
+        ++w.seg;
+        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
+        w.e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
+        w.ne = cnt != 0u;
+        const uint64_t nem = __ballot(w.ne);
+        wave_lds_sync();
+        if (w.ne) {
+            const uint32_t rk = (uint32_t)__popcll(nem & lt);
+            S.pb[rk] = st - w.excl;
+            S.qi[rk] = myqi;
+        }
+        w.base = (uint32_t)__popcll(__ballot(w.ne && w.excl < a));
+        w.be = g.bs[j + 1];
+        w.nj = w.be - g.bs[j];
+        w.t0 = a;
+        w.in_seg = a < w.e;
+    }
+    uint64_t M[VT];
+    step_starts<VT>(S.flag, lane, w.ne, w.excl, w.t0, M);
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        // decision word of the sub-round (uniform: scalar registers)
+        uint64_t x = S.bits[w.word + i];
+        x = (w.t0 + 64u * i < w.e) ? x : 0ull;
+        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+        const uint32_t rk = (w.base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
+        w.base += (uint32_t)__popcll(M[i]);
+        const bool mine = (m >> lane) & 1ull;
+        const uint32_t p = mine ? position_pb(S.pb[rk], w.t0 + 64u * i + lane, w.be, w.nj) : w.be - 1u;
+        s.qi[i] = S.qi[rk];
+        s.wi[i] = ld<WIDE>(g.idx, p);
+        s.off[i] = mine ? (w.out_rel + (uint32_t)__popcll(m & lt)) * 8u : NO_STORE;
+        w.out_rel += (uint32_t)__popcll(m);
+    }
+    w.word += (w.e - w.t0 < 64u * VT) ? (w.e - w.t0 + 63u) / 64u : (uint32_t)VT;
+    w.t0 += 64u * VT;
+    w.in_seg = w.t0 < w.e;
+    s.valid = true;
+}
+
+__device__ __forceinline__ void emit_store(const EmitStep &s, __amdgpu_buffer_rsrc_t out) {
+#pragma unroll
+    for (int i = 0; i < VT_EMIT; ++i) {
+        const uint32_t lo = s.qi[i] < s.wi[i] ? s.qi[i] : s.wi[i];
+        const uint32_t hi = s.qi[i] < s.wi[i] ? s.wi[i] : s.qi[i];
+        const u32x2_t v = {lo, hi};
+        __builtin_amdgcn_raw_buffer_store_b64(v, out, (int)s.off[i], 0, STORE_NT);
+    }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int lane, EmitSmem &S) {
+    const Geo &g = A.geo;
+    const uint32_t todo = uniform_u32(A.unit_edges[unit]);
     if (todo == 0) return;
     const UnitSetup u = unit_setup(A, unit, lane);
     const uint32_t myqi = u.valid ? g.idx[u.v] : 0u;
-    for (int k = lane; k < BITW; k += 64) S.bits[k] = A.bits[unit * BITW + k];
+    for (int k = lane; k < BITW + VT_EMIT; k += 64) S.bits[k] = k < BITW ? A.bits[unit * BITW + k] : 0ull;
 #pragma unroll
-    for (int i = 0; i < VT; ++i) S.flag[i * 64 + lane] = 0u;
+    for (int i = 0; i < VT_EMIT; ++i) S.flag[i * 64 + lane] = 0u;
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t out_at = A.unit_edge_off[unit];
-    const uint64_t out_end = out_at + todo;
+    const uint64_t at = uniform_u64(A.unit_edge_off[unit]);  // the resource must sit in scalar registers
+    uint64_t cap = A.out_capacity > at ? A.out_capacity - at : 0ull;
+    cap = cap < todo ? cap : todo;
+    const __amdgpu_buffer_rsrc_t out =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(A.out + at), 0, (int)(cap * 8u), BUFFER_WORD3);
 
-    uint64_t pos = u.pos;
-    uint32_t word = 0;
-    for (int j = u.jstart; j < g.B && pos < u.r1 && out_at < out_end; ++j) {
-        uint32_t st, cnt, excl, tot;
-        slab_windows(g, A, u, j, st, cnt, excl, tot);
-        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
-        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
-        const bool ne = cnt != 0u;
-        const uint64_t nem = __ballot(ne);
-        wave_lds_sync();
-        if (ne) {
-            const uint32_t rk = (uint32_t)__popcll(nem & lt);
-            S.pb[rk] = st - excl;
-            S.qi[rk] = myqi;
-        }
-        uint32_t base = (uint32_t)__popcll(__ballot(ne && excl < a));
-        const uint32_t be = g.bs[j + 1], nj = be - g.bs[j];
-        for (uint32_t t0 = a; t0 < e && out_at < out_end; t0 += 64u * VT) {
-            uint64_t M[VT];
-            step_starts<VT>(S.flag, lane, ne, excl, t0, M);
-            // decision words of the sub-rounds (uniform: kept in scalar registers)
-            uint64_t m[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint64_t x = (t0 + 64u * i < e) ? S.bits[word + i] : 0ull;
-                m[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-            }
-            // all gathers first (unconditional, in-bounds dummy for lanes without an edge) ...
-            uint32_t wi[VT], qi[VT];
-            bool mine_[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t rk = (base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
-                base += (uint32_t)__popcll(M[i]);
-                mine_[i] = (m[i] >> lane) & 1ull;
-                const uint32_t p = mine_[i] ? position_pb(S.pb[rk], t0 + 64u * i + lane, be, nj) : be - 1u;
-                qi[i] = S.qi[rk];
-                wi[i] = ld<WIDE>(g.idx, p);
-            }
-            // ... then all stores back to back
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t lo = qi[i] < wi[i] ? qi[i] : wi[i], hi = qi[i] < wi[i] ? wi[i] : qi[i];
-                const uint64_t at = out_at + (uint64_t)__popcll(m[i] & lt);
-                if (mine_[i] && at < A.out_capacity) A.out[at] = make_int2((int)lo, (int)hi);
-                out_at += (uint64_t)__popcll(m[i]);
-            }
-            word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
-        }
-        pos += tot;
+    prefetch_windows(A, u, lane, S.wpre);
+    EmitWalk w;
+    w.segs = u.segmask;
+    w.seg = 0;
+    w.t0 = w.e = w.base = w.word = w.be = w.nj = w.excl = w.out_rel = 0u;
+    w.ne = w.in_seg = false;
+    EmitStep s0, s1;
+    emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s0);
+    while (s0.valid) {
+        emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s1);  // gathers of the next step ...
+        emit_store(s0, out);                                            // ... in flight over these stores
+        if (!s1.valid) break;
+        emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s0);
+        emit_store(s1, out);
     }
 }
 
