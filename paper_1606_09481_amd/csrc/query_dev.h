@@ -367,7 +367,7 @@ constexpr int VT_COUNT = RHG_VT_COUNT;
 constexpr int VT_EMIT = RHG_VT_EMIT;
 
 template <int VT>
-__device__ __forceinline__ void step_starts(uint32_t *flags, int lane, bool nonempty, uint32_t excl, uint32_t t0,
+__device__ __forceinline__ void step_starts(uint8_t *flags, int lane, bool nonempty, uint32_t excl, uint32_t t0,
                                             uint64_t (&M)[VT]) {
     if (nonempty && excl >= t0 && excl - t0 < 64u * VT) flags[excl - t0] = 1u;
     wave_lds_sync();
@@ -404,17 +404,20 @@ __device__ __forceinline__ uint32_t position_pb(uint32_t pb, uint32_t t, uint32_
 // Count pass: decide every candidate of the unit, record the decisions as
 // one bitmap word per 64-candidate round, count edges.
 // Per-wavefront LDS of the count pass.
+// (FP32 operands only in the filter form, to keep the FP64 form's LDS, and
+// with it the workgroups per CU, down.)
+template <int FP32>
 struct CountSmem {
     uint32_t pb[64];    // per rank: start position - flattened offset
-    uint32_t flag[64 * VT_COUNT];
+    uint8_t flag[64 * VT_COUNT];
     double qd[5][64];   // per rank: query operands
-    float qf[3][64];
+    float qf[FP32 ? 3 : 1][64];
     unsigned long long bits[BITW];
     uint2 wpre[SEG_PRE][64];
 };
 
 template <int FP32, bool WIDE>
-__device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, int lane, CountSmem &S) {
+__device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, int lane, CountSmem<FP32> &S) {
     constexpr int VT = VT_COUNT;
     const Geo &g = A.geo;
     const UnitSetup u = unit_setup(A, unit, lane);
@@ -543,7 +546,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
 // Per-wavefront LDS of the emit pass.
 struct EmitSmem {
     uint32_t pb[64];
-    uint32_t flag[64 * VT_EMIT];
+    uint8_t flag[64 * VT_EMIT];
     uint32_t qi[64];
     unsigned long long bits[BITW + VT_EMIT];
     uint2 wpre[SEG_PRE][64];

@@ -29,7 +29,8 @@ struct ScanSmem {
 };
 union PhaseSmem {
     SortSmem sort;
-    CountSmem count[SM_WAVES];
+    CountSmem<0> count0[SM_WAVES];
+    CountSmem<1> count1[SM_WAVES];
     EmitSmem emit[SM_WAVES];
 };
 
@@ -315,8 +316,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
 
     // ---- a5: count
     for (uint64_t u = w; u < U; u += SM_WAVES) {
-        if (D.fp32) count_unit<1, false>(sA, u, lane, P.count[w]);
-        else count_unit<0, false>(sA, u, lane, P.count[w]);
+        if (D.fp32) count_unit<1, false>(sA, u, lane, P.count1[w]);
+        else count_unit<0, false>(sA, u, lane, P.count0[w]);
     }
     __syncthreads();
 
