@@ -46,6 +46,10 @@ void scan_u32(const uint32_t *in, uint64_t *out, uint64_t len, void *scratch, hi
 
 // Work units: units per batch = ceil(cand / UNIT).
 void units_per_batch(const uint64_t *batch_cand, uint64_t nb, uint64_t *nunits, hipStream_t st);
+// boff / uoff (nb + 1 each): exclusive scans of the candidates and of the
+// units per batch (nunits: nb scratch, used above one workgroup's size).
+void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nunits, uint64_t *uoff, void *scratch,
+                hipStream_t st);
 void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units, uint32_t *unit_batch,
                      hipStream_t st);
 

@@ -308,6 +308,8 @@ void geo_static(const Plan &pl, Geo &g) {
 
 int key_bits_for(int B) { return QBITS + std::max(1, ceil_log2((uint64_t)B)); }
 
+constexpr uint64_t UNIT_ORDER_MIN = 8192;
+
 rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipSetDevice(c->device));
     (void)hipGetLastError();  // launch errors checked below are this call's own
@@ -412,9 +414,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     void *scan_scr = c->buf(S_SCANSCR, rhgk::scan_scratch_bytes(std::max<uint64_t>(nb, 1ull << 22)));
     if (!scan_scr) return RHG_ENOMEM;
     rhgk::plan(g, win, bcand, bsoff, st);
-    rhgk::scan_u64(bcand, boff, nb, scan_scr, st);
-    rhgk::units_per_batch(bcand, nb, nunits, st);
-    rhgk::scan_u64(nunits, uoff, nb, scan_scr, st);
+    rhgk::plan_scans(bcand, nb, boff, nunits, uoff, scan_scr, st);
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN1], st));
     uint64_t *pin = (uint64_t *)c->pinned;
     RHG_HIP(hipMemcpyAsync(pin + 0, boff + nb, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -456,9 +456,13 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(uorder2, uint32_t, S_UORDER2, std::max<uint64_t>(U, 1));
     void *usort = c->buf(S_SORTSCR2, rhgk::sort_scratch_bytes(std::max<uint64_t>(U, 1)));
     if (!usort) return RHG_ENOMEM;
+    // sector order of the units (for L2 reuse across a large plan; below
+    // UNIT_ORDER_MIN units the tables fit in cache and the launches cost more)
     qa.unit_order = nullptr;
-    rhgk::unit_order(qa, ukey, uorder, ukey2, uorder2, usort, st);
-    qa.unit_order = uorder;
+    if (U >= UNIT_ORDER_MIN) {
+        rhgk::unit_order(qa, ukey, uorder, ukey2, uorder2, usort, st);
+        qa.unit_order = uorder;
+    }
     RHG_HIP(hipEventRecord(c->ev[EV_QCOUNT0], st));
     rhgk::query_count(qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));

@@ -81,6 +81,49 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const T *in, uint64_t 
     if (base < len && base + SC_ITEMS >= len) out[len] = run;  // the thread holding the last value
 }
 
+// Short arrays (len <= SCAN_ONE_MAX, one chunk of 16384): one workgroup of
+// 1024 threads scans them in one launch (the three-launch form costs more
+// than the work at this size; longer arrays keep it, since one workgroup
+// walking many chunks is slower than three launches).
+constexpr int S1_THREADS = 1024;
+constexpr int S1_ITEMS = 16;
+constexpr uint64_t SCAN_ONE_MAX = 1ull << 14;
+
+template <typename T>
+__global__ __launch_bounds__(S1_THREADS) void k_scan_one(const T *in, uint64_t len, uint64_t *out) {
+    __shared__ uint64_t wsum[S1_THREADS / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    uint64_t carry = 0;
+    for (uint64_t chunk = 0; chunk < len; chunk += (uint64_t)S1_THREADS * S1_ITEMS) {
+        const uint64_t base = chunk + (uint64_t)threadIdx.x * S1_ITEMS;
+        uint64_t v[S1_ITEMS];
+        uint64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < S1_ITEMS; ++i) {
+            v[i] = (base + i < len) ? (uint64_t)in[base + i] : 0;
+            s += v[i];
+        }
+        const uint64_t incl = wave_incl_scan_u64(s);
+        if (l == 63) wsum[w] = incl;
+        __syncthreads();
+        uint64_t before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < S1_THREADS / 64; ++k) {
+            if (k < w) before += wsum[k];
+            tot += wsum[k];
+        }
+        __syncthreads();
+        uint64_t run = carry + before + incl - s;
+#pragma unroll
+        for (int i = 0; i < S1_ITEMS; ++i) {
+            if (base + i < len) out[base + i] = run;
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[len] = carry;
+}
+
 size_t scan_scratch_bytes(uint64_t len) {
     uint64_t ntiles = (len + SC_TILE - 1) / SC_TILE;
     return (ntiles + 1) * sizeof(uint64_t);
@@ -90,6 +133,10 @@ template <typename T>
 static void scan_impl(const T *in, uint64_t *out, uint64_t len, void *scratch, hipStream_t st) {
     if (len == 0) {
         (void)hipMemsetAsync(out, 0, sizeof(uint64_t), st);
+        return;
+    }
+    if (len <= SCAN_ONE_MAX) {
+        hipLaunchKernelGGL(k_scan_one<T>, dim3(1), dim3(S1_THREADS), 0, st, in, len, out);
         return;
     }
     uint64_t ntiles = (len + SC_TILE - 1) / SC_TILE;
@@ -113,6 +160,71 @@ __global__ __launch_bounds__(256) void k_units(const uint64_t *cand, uint64_t nb
 
 void units_per_batch(const uint64_t *cand, uint64_t nb, uint64_t *nunits, hipStream_t st) {
     if (nb) hipLaunchKernelGGL(k_units, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, cand, nb, nunits);
+}
+
+// Both scans of the plan's batch totals in one workgroup (short plans):
+// boff = exclusive scan of the candidates per batch, uoff = exclusive scan of
+// the units per batch (ceil(candidates / UNIT)).
+__global__ __launch_bounds__(S1_THREADS) void k_scan_plan(const uint64_t *cand, uint64_t nb, uint64_t *boff,
+                                                          uint64_t *uoff) {
+    __shared__ uint64_t wsum[2][S1_THREADS / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    uint64_t carry_c = 0, carry_u = 0;
+    for (uint64_t chunk = 0; chunk < nb; chunk += (uint64_t)S1_THREADS * S1_ITEMS) {
+        const uint64_t base = chunk + (uint64_t)threadIdx.x * S1_ITEMS;
+        uint64_t c[S1_ITEMS];
+        uint64_t sc = 0, su = 0;
+#pragma unroll
+        for (int i = 0; i < S1_ITEMS; ++i) {
+            c[i] = (base + i < nb) ? cand[base + i] : 0;
+            sc += c[i];
+            su += (c[i] + UNIT - 1) / UNIT;
+        }
+        const uint64_t ic = wave_incl_scan_u64(sc), iu = wave_incl_scan_u64(su);
+        if (l == 63) {
+            wsum[0][w] = ic;
+            wsum[1][w] = iu;
+        }
+        __syncthreads();
+        uint64_t bc = 0, bu = 0, tc = 0, tu = 0;
+#pragma unroll
+        for (int k = 0; k < S1_THREADS / 64; ++k) {
+            if (k < w) {
+                bc += wsum[0][k];
+                bu += wsum[1][k];
+            }
+            tc += wsum[0][k];
+            tu += wsum[1][k];
+        }
+        __syncthreads();
+        uint64_t rc = carry_c + bc + ic - sc, ru = carry_u + bu + iu - su;
+#pragma unroll
+        for (int i = 0; i < S1_ITEMS; ++i) {
+            if (base + i < nb) {
+                boff[base + i] = rc;
+                uoff[base + i] = ru;
+            }
+            rc += c[i];
+            ru += (c[i] + UNIT - 1) / UNIT;
+        }
+        carry_c += tc;
+        carry_u += tu;
+    }
+    if (threadIdx.x == 0) {
+        boff[nb] = carry_c;
+        uoff[nb] = carry_u;
+    }
+}
+
+void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nunits, uint64_t *uoff, void *scratch,
+                hipStream_t st) {
+    if (nb && nb <= SCAN_ONE_MAX) {
+        hipLaunchKernelGGL(k_scan_plan, dim3(1), dim3(S1_THREADS), 0, st, cand, nb, boff, uoff);
+        return;
+    }
+    scan_u64(cand, boff, nb, scratch, st);
+    units_per_batch(cand, nb, nunits, st);
+    scan_u64(nunits, uoff, nb, scratch, st);
 }
 
 // unit_off[b] .. unit_off[b+1]-1 are the units of batch b: unit u belongs to
