@@ -8,6 +8,17 @@
 namespace rhgk {
 using namespace rhgd;
 
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    return ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32) | uniform_u32((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+}
+
 // Half-width of the window of query v in slab j >= 1.  The bound is
 //   s = (Kw - cosh(r_v - c_j)) / (2 sinh r_v sinh c_j),  half-width 2 asin(sqrt s),
 // with cosh(r_v - c_j) = (e^{r_v} e^{-c_j} + e^{-r_v} e^{c_j}) / 2 from the
@@ -121,9 +132,13 @@ __device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j,
 // One wavefront plans one batch b of 64 sorted queries (lane = query b*64+lane).
 __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off,
                                            uint32_t b, int lane) {
+    // b and the slab index are wave-uniform: kept in scalar registers, the
+    // per-slab geometry (offsets, constants, bucket layout) is read with
+    // scalar loads instead of one dependent vector load chain per slab
+    b = uniform_u32(b);
     const uint32_t s = b * BATCH + (uint32_t)lane;
     const bool valid = s < g.n;
-    const int jmin = (int)(g.keys[b * BATCH] >> QBITS);
+    const int jmin = (int)uniform_u32(g.keys[b * BATCH] >> QBITS);
     int i = g.B;
     uint32_t qv = 0;
     double thv = 0.0;
@@ -231,17 +246,6 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
     }
 }
 
-__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-}
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
-    return ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32) | uniform_u32((uint32_t)x);
-}
-__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int l) {
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-}
-
 // Per-unit setup shared by the count and emit passes: the unit's batch and
 // flattened range [r0, r1), the lane's query, the first slab whose segment
 // reaches past r0, and the slab segments the unit meets: bit k of segmask is
@@ -262,10 +266,13 @@ struct UnitSetup {
 __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
     const Geo &g = A.geo;
     UnitSetup u;
-    u.b = A.unit_batch[unit];
-    const uint64_t chunk = unit - A.unit_off[u.b];
+    // unit, batch and range are wave-uniform: scalar registers, so the walk
+    // over slabs indexes the geometry with scalar loads
+    unit = uniform_u64(unit);
+    u.b = uniform_u32(A.unit_batch[unit]);
+    const uint64_t chunk = unit - uniform_u64(A.unit_off[u.b]);
     u.r0 = chunk * UNIT;
-    const uint64_t bc = A.batch_cand[u.b];
+    const uint64_t bc = uniform_u64(A.batch_cand[u.b]);
     u.r1 = (u.r0 + UNIT < bc) ? u.r0 + UNIT : bc;
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
