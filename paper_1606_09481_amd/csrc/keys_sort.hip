@@ -8,6 +8,8 @@
 // Searching windows on the same quantised keys keeps every window a superset
 // of the exact angular interval, so the key resolution only affects how many
 // candidates are tested, never the edge set.
+#include <algorithm>
+
 #include "rhg_kernels.h"
 
 namespace rhgk {
@@ -62,111 +64,204 @@ void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits.  Per pass: tile histograms (digit-major),
-// exclusive scan, stable scatter.  A tile is 4096 keys: 4 wavefronts x 16
-// items x 64 lanes, position = tile + wave*1024 + item*64 + lane.
+// LSD radix sort, 8-bit digits, one kernel per digit pass.
+//
+// The digit counts of every pass do not depend on the order of the keys, so
+// one read of the keys gives them all (k_digit_counts).  A pass then takes
+// its 4096-key tiles in ticket order (an atomic counter: a workgroup only
+// ever waits for tiles whose tickets were drawn before its own, by
+// workgroups already running), ranks its keys stably per digit (per-wave
+// ballots), and finds, per digit, how many keys of that digit the earlier
+// tiles hold by a decoupled look-back over their published per-digit
+// counts: each tile publishes its own count at once (LOCAL) and its running
+// total once known (TOTAL), so a look-back stops at the first TOTAL and adds
+// the LOCAL counts it passes.  The keys are then staged in LDS in digit order
+// and written out in runs of consecutive addresses per digit.
+//
+// Status words are 64-bit (2-bit flag, 62-bit count) and go through
+// device-coherent atomic loads and stores.  A look-back that sees no progress
+// for SORT_SPIN_LIMIT polls (never expected) raises the error flag and goes
+// on, so no workgroup waits forever.
 // ---------------------------------------------------------------------------
 constexpr int S_THREADS = 256;
 constexpr int S_ITEMS = 16;
 constexpr int S_TILE = S_THREADS * S_ITEMS;
+constexpr int S_MAX_PASSES = 4;
+constexpr uint64_t ST_LOCAL = 1ull << 62, ST_TOTAL = 2ull << 62, ST_VALUE = (1ull << 62) - 1;
+constexpr uint32_t SORT_SPIN_LIMIT = 1u << 22;
 
-__global__ __launch_bounds__(S_THREADS) void k_sort_hist(const uint32_t *keys, uint32_t n, int shift,
-                                                         uint64_t *hist, uint32_t ntiles) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t base = blockIdx.x * S_TILE;
-#pragma unroll
-    for (int i = 0; i < S_ITEMS; ++i) {
-        uint32_t p = base + i * S_THREADS + threadIdx.x;
-        if (p < n) atomicAdd(&h[(keys[p] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+// Scratch layout: [tickets (S_MAX_PASSES u32) | error u32 | pad] [digit counts S_MAX_PASSES x 256 u32]
+//                 [status S_MAX_PASSES x ntiles x 256 u64]
+struct SortScratch {
+    uint32_t *tickets;
+    uint32_t *error;
+    uint32_t *counts;
+    uint64_t *status;
+};
+static SortScratch sort_scratch(void *scratch, uint32_t ntiles) {
+    SortScratch x;
+    char *p = (char *)scratch;
+    x.tickets = (uint32_t *)p;
+    x.error = x.tickets + S_MAX_PASSES;
+    x.counts = (uint32_t *)(p + 256);
+    x.status = (uint64_t *)(p + 256 + S_MAX_PASSES * 256 * sizeof(uint32_t));
+    (void)ntiles;
+    return x;
 }
 
-__global__ __launch_bounds__(S_THREADS) void k_sort_scatter(const uint32_t *keys, const uint32_t *vals,
-                                                            uint32_t *keys_out, uint32_t *vals_out, uint32_t n,
-                                                            int shift, const uint64_t *offs, uint32_t ntiles) {
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t toff[256];
+__global__ __launch_bounds__(S_THREADS) void k_digit_counts(const uint32_t *keys, uint32_t n, int passes,
+                                                            uint32_t *counts) {
+    __shared__ uint32_t h[S_MAX_PASSES][256];
+    for (int q = 0; q < S_MAX_PASSES; ++q) h[q][threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * S_THREADS + threadIdx.x; i < n; i += gridDim.x * S_THREADS) {
+        const uint32_t k = keys[i];
+        for (int q = 0; q < passes; ++q) atomicAdd(&h[q][(k >> (8 * q)) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int q = 0; q < passes; ++q)
+        if (h[q][threadIdx.x]) atomicAdd(&counts[q * 256 + threadIdx.x], h[q][threadIdx.x]);
+}
+
+// Exclusive scan of 256 values, one per thread of the workgroup (4 wavefronts).
+__device__ __forceinline__ uint32_t block_excl_256(uint32_t x, uint32_t *wtot) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t incl = wave_incl_scan_u32(x);
+    if (l == 63) wtot[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += wtot[k];
+    __syncthreads();
+    return before + incl - x;
+}
+
+__global__ __launch_bounds__(S_THREADS) void k_sort_pass(const uint32_t *keys, const uint32_t *vals,
+                                                         uint32_t *keys_out, uint32_t *vals_out, uint32_t n,
+                                                         int shift, const uint32_t *counts, uint64_t *status,
+                                                         uint32_t *ticket, uint32_t *error) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t lstart[256], gbase[256], wtot[4];
+    __shared__ uint32_t sk[S_TILE], sv[S_TILE];
+    __shared__ uint32_t sh_tile;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (threadIdx.x == 0) sh_tile = atomicAdd(ticket, 1u);
     for (int d = l; d < 256; d += 64) wcnt[w][d] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * S_TILE + w * (S_ITEMS * 64);
+    const uint32_t tile = sh_tile;
+    const uint32_t base = tile * S_TILE + w * (S_ITEMS * 64);
     const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
     uint32_t k[S_ITEMS], v[S_ITEMS], rk[S_ITEMS];
 #pragma unroll
     for (int i = 0; i < S_ITEMS; ++i) {
-        uint32_t p = base + i * 64 + l;
-        bool ok = p < n;
+        const uint32_t p = base + i * 64 + l;
+        const bool ok = p < n;
         k[i] = ok ? keys[p] : 0u;
         v[i] = ok ? vals[p] : 0u;
     }
+    // stable rank per wavefront and digit
 #pragma unroll
     for (int i = 0; i < S_ITEMS; ++i) {
-        uint32_t p = base + i * 64 + l;
-        bool ok = p < n;
-        uint32_t d = (k[i] >> shift) & 255u;
+        const uint32_t p = base + i * 64 + l;
+        const bool ok = p < n;
+        const uint32_t d = (k[i] >> shift) & 255u;
         uint64_t m = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
             m &= bit ? bb : ~bb;
         }
-        uint32_t below = (uint32_t)__popcll(m & lt);
-        uint32_t prev = wcnt[w][d];
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        const uint32_t prev = wcnt[w][d];
         rk[i] = prev + below;
         __builtin_amdgcn_wave_barrier();
         if (ok && below == 0) wcnt[w][d] = prev + (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        const int d = threadIdx.x;
-        uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d];
-        wcnt[0][d] = 0;
-        wcnt[1][d] = c0;
-        wcnt[2][d] = c0 + c1;
-        wcnt[3][d] = c0 + c1 + c2;
-        toff[d] = (uint32_t)offs[(uint64_t)d * ntiles + blockIdx.x];
+    // per digit (thread d): tile count, wavefront prefixes, publish, look back
+    const int d = threadIdx.x;
+    const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+    const uint32_t h = c0 + c1 + c2 + c3;
+    uint64_t *my = status + (uint64_t)tile * 256 + d;
+    __hip_atomic_store(my, (tile == 0 ? ST_TOTAL : ST_LOCAL) | (uint64_t)h, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t ls = block_excl_256(h, wtot);
+    const uint32_t gd = block_excl_256(counts[d], wtot);
+    uint64_t before = 0;
+    if (tile > 0) {
+        uint32_t k2 = tile - 1, spins = 0;
+        for (;;) {
+            const uint64_t st = __hip_atomic_load(status + (uint64_t)k2 * 256 + d, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = st & ~ST_VALUE;
+            if (flag == 0) {
+                if (++spins > SORT_SPIN_LIMIT) {
+                    atomicOr(error, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            before += st & ST_VALUE;
+            if (flag == ST_TOTAL || k2 == 0) break;
+            --k2;
+        }
+        __hip_atomic_store(my, ST_TOTAL | (before + h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    wcnt[0][d] = 0;
+    wcnt[1][d] = c0;
+    wcnt[2][d] = c0 + c1;
+    wcnt[3][d] = c0 + c1 + c2;
+    lstart[d] = ls;
+    gbase[d] = gd + (uint32_t)before;
     __syncthreads();
+    // stage in digit order, then write runs of consecutive addresses
 #pragma unroll
     for (int i = 0; i < S_ITEMS; ++i) {
-        uint32_t p = base + i * 64 + l;
+        const uint32_t p = base + i * 64 + l;
         if (p < n) {
-            uint32_t d = (k[i] >> shift) & 255u;
-            uint32_t dst = toff[d] + wcnt[w][d] + rk[i];
-            keys_out[dst] = k[i];
-            vals_out[dst] = v[i];
+            const uint32_t dd = (k[i] >> shift) & 255u;
+            const uint32_t lp = lstart[dd] + wcnt[w][dd] + rk[i];
+            sk[lp] = k[i];
+            sv[lp] = v[i];
         }
+    }
+    __syncthreads();
+    const uint32_t valid = (n - tile * S_TILE < (uint32_t)S_TILE) ? n - tile * S_TILE : (uint32_t)S_TILE;
+    for (uint32_t j = threadIdx.x; j < valid; j += S_THREADS) {
+        const uint32_t key = sk[j];
+        const uint32_t dd = (key >> shift) & 255u;
+        const uint32_t dst = gbase[dd] + (j - lstart[dd]);
+        keys_out[dst] = key;
+        vals_out[dst] = sv[j];
     }
 }
 
+uint32_t *sort_error_flag(void *scratch) { return sort_scratch(scratch, 0).error; }
+
 size_t sort_scratch_bytes(uint64_t n) {
-    uint64_t ntiles = (n + S_TILE - 1) / S_TILE;
-    uint64_t len = 256 * (ntiles ? ntiles : 1);
-    return 2 * (len + 1) * sizeof(uint64_t) + scan_scratch_bytes(len) + 256;
+    const uint64_t ntiles = (n + S_TILE - 1) / S_TILE;
+    return 256 + S_MAX_PASSES * 256 * sizeof(uint32_t) +
+           (uint64_t)S_MAX_PASSES * (ntiles ? ntiles : 1) * 256 * sizeof(uint64_t);
 }
 
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                 int bits, hipStream_t st) {
     if (n < 2) return;
-    uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
-    uint64_t len = 256ull * ntiles;
-    uint64_t *hist = (uint64_t *)scratch;
-    uint64_t *offs = hist + (len + 1);
-    void *sscr = (void *)(offs + (len + 1));
+    const uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
     int passes = (bits + 7) / 8;
+    if (passes > S_MAX_PASSES) passes = S_MAX_PASSES;
+    const SortScratch x = sort_scratch(scratch, ntiles);
+    const size_t status_bytes = (size_t)passes * ntiles * 256 * sizeof(uint64_t);
+    // tickets, error flag, digit counts and the status words of every pass start at zero
+    (void)hipMemsetAsync(scratch, 0, 256 + S_MAX_PASSES * 256 * sizeof(uint32_t) + status_bytes, st);
+    const unsigned cblocks = (unsigned)std::min<uint64_t>(1024, (n + S_THREADS * 16 - 1) / (S_THREADS * 16));
+    hipLaunchKernelGGL(k_digit_counts, dim3(cblocks), dim3(S_THREADS), 0, st, keys, (uint32_t)n, passes, x.counts);
     uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
     for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
-        hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(S_THREADS), 0, st, ka, (uint32_t)n, shift, hist, ntiles);
-        scan_u64(hist, offs, len, sscr, st);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, shift,
-                           offs, ntiles);
+        hipLaunchKernelGGL(k_sort_pass, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, 8 * p,
+                           x.counts + p * 256, x.status + (size_t)p * ntiles * 256, x.tickets + p, x.error);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }

@@ -20,6 +20,9 @@ void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStrea
 // a3: stable LSD radix sort of (keys, vals), `bits` low key bits, 8 per pass;
 // the result ends in (keys, vals); tmp buffers of n each; scratch from
 // sort_scratch_bytes.
+// Device flag (u32) a sort raises if a look-back made no progress for its
+// whole spin budget (never expected; the sorted output is then invalid).
+uint32_t *sort_error_flag(void *scratch);
 size_t sort_scratch_bytes(uint64_t n);
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                 int bits, hipStream_t st);

@@ -367,9 +367,12 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
 
     // slab sizes -> layout of windows and bucket index
     RHG_HIP(hipMemcpyAsync(c->pinned, hist, sizeof(uint32_t) * (MAX_BANDS + 8), hipMemcpyDeviceToHost, st));
+    uint32_t *sort_err = (uint32_t *)((char *)c->pinned + 1024);
+    RHG_HIP(hipMemcpyAsync(sort_err, rhgk::sort_error_flag(sort_scr), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipStreamSynchronize(st));
     const uint32_t *hh = (const uint32_t *)c->pinned;
     if (hh[MAX_BANDS + 4] != 0) return RHG_EINVAL;  // coordinates out of range
+    if (*sort_err != 0) return RHG_EDEVICE;         // a sort pass gave up waiting (never expected)
 
     Geo &g = pl.geo;
     geo_static(pl, g);
@@ -470,8 +473,13 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
     RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    uint32_t *usort_err = (uint32_t *)((char *)c->pinned + 1028);
+    *usort_err = 0;
+    if (qa.unit_order)
+        RHG_HIP(hipMemcpyAsync(usort_err, rhgk::sort_error_flag(usort), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipStreamSynchronize(st));
     RHG_HIP(hipGetLastError());
+    if (*usort_err != 0) return RHG_EDEVICE;
     pl.m = pin[2];
     pl.rechecks = pin[3];
     pl.disagreements = pin[4];
