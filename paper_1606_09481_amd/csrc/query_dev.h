@@ -485,40 +485,43 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
         for (uint32_t t0 = a; t0 < e; t0 += 64u * VT) {
             uint64_t M[VT];
             step_starts<VT>(S.flag, lane, ne, excl, t0, M);
+            // Lanes past the segment's end take a dummy candidate (position bs,
+            // rank masked into range) whose result is dropped.
             uint32_t p[VT], rk[VT];
             bool act[VT];
 #pragma unroll
             for (int i = 0; i < VT; ++i) {
                 const uint32_t t = t0 + 64u * i + lane;
                 act[i] = t < e;
-                rk[i] = base - 1u + (uint32_t)__popcll(M[i] & le);
+                rk[i] = (base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
                 base += (uint32_t)__popcll(M[i]);
-                p[i] = act[i] ? position_pb(S.pb[rk[i]], t, be, nj) : bs;
+                const uint32_t pp = position_pb(S.pb[rk[i]], t, be, nj);
+                p[i] = act[i] ? pp : bs;
             }
             Cand c[VT];
 #pragma unroll
             for (int i = 0; i < VT; ++i) load_cand<FP32, WIDE>(g, p[i], c[i]);
 #pragma unroll
             for (int i = 0; i < VT; ++i) {
-                int flag = 0;
-                if (act[i]) {
-                    Qv q;
-                    q.hep = S.qd[0][rk[i]];
-                    q.hem = S.qd[1][rk[i]];
-                    q.sh2 = S.qd[2][rk[i]];
-                    q.hs = S.qd[3][rk[i]];
-                    q.hc = S.qd[4][rk[i]];
-                    if (FP32) {
-                        q.hep32 = S.qf[0][rk[i]];
-                        q.hem32 = S.qf[1][rk[i]];
-                        q.sh2_32 = S.qf[2][rk[i]];
-                    }
-                    const uint32_t r = edge_test<FP32>(g, q, c[i], p[i], A.exhaustive);
-                    flag = (int)(r & 1u);
-                    if (FP32) {
-                        rechecks += (r >> 1) & 1u;
-                        disagree += (r >> 2) & 1u;
-                    }
+                Qv q;
+                q.hep = S.qd[0][rk[i]];
+                q.hem = S.qd[1][rk[i]];
+                q.sh2 = S.qd[2][rk[i]];
+                q.hs = S.qd[3][rk[i]];
+                q.hc = S.qd[4][rk[i]];
+                if (FP32) {
+                    q.hep32 = S.qf[0][rk[i]];
+                    q.hem32 = S.qf[1][rk[i]];
+                    q.sh2_32 = S.qf[2][rk[i]];
+                }
+                // FP32 filter: test every lane and mask (the loads issue together);
+                // FP64: lanes past the end skip the test (measured faster there)
+                const uint32_t r = FP32 ? (edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) & (act[i] ? 7u : 0u))
+                                        : (act[i] ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
+                const int flag = (int)(r & 1u);
+                if (FP32) {
+                    rechecks += (r >> 1) & 1u;
+                    disagree += (r >> 2) & 1u;
                 }
                 const uint64_t m = __ballot(flag);
                 found += (uint32_t)__popcll(m);
