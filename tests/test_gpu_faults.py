@@ -1,0 +1,99 @@
+"""Failure handling on the GPU, forced from the host.
+
+A caller allocator hook (rhg_ctx_set_allocator) refuses the k-th device
+allocation of a generation, for every k the generation makes: the call must
+return RHG_ENOMEM (no crash, no partial graph), the same context must then
+produce the right graph once allocations succeed again, and destroying it
+must return every block to the caller (no leak).  All kernels run normally;
+only the host-side allocation fails.
+"""
+import numpy as np
+import pytest
+
+from paper_1606_09481_amd import rhg
+
+pytestmark = pytest.mark.gpu
+
+
+class TorchBlocks:
+    """Device blocks from torch's caching allocator; refuses after `limit` grants."""
+
+    def __init__(self, limit):
+        self.limit = limit
+        self.granted = 0
+        self.live = {}
+        self.unknown = 0  # frees of pointers never granted (callback errors do not propagate)
+
+    def alloc(self, nbytes):
+        import torch
+        if self.granted >= self.limit:
+            return 0
+        self.granted += 1
+        t = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(self, ptr):
+        if self.live.pop(ptr, None) is None:
+            self.unknown += 1
+
+
+def _ctx_with(blocks):
+    import torch
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())  # torch's stream: its blocks are reused in order
+    rhg.rhg_ctx_set_allocator(c, blocks.alloc, blocks.free)
+    return c
+
+
+def test_refused_allocation_at_every_point():
+    import torch
+    rhg.load()
+    torch.cuda.set_device(0)
+    p = rhg.params(50_000, 0.9, kbar=12, seed=3, precision=rhg.RHG_FP32_RECHECK)
+    blocks = TorchBlocks(10 ** 9)
+    c = _ctx_with(blocks)
+    g = rhg.rhg_generate(c, p)
+    ref = rhg.rhg_graph_copy_edges(g)
+    rhg.rhg_graph_free(g)
+    rhg.rhg_ctx_destroy(c)
+    total = blocks.granted
+    assert not blocks.live and blocks.unknown == 0 and total > 5
+    print("allocations per generation:", total, flush=True)
+    for k in range(total):
+        blocks = TorchBlocks(k)
+        c = _ctx_with(blocks)
+        try:
+            with pytest.raises(rhg.RhgError) as ei:
+                rhg.rhg_generate(c, p)
+            assert ei.value.status == rhg.RHG_ENOMEM, "refusal %d: %s" % (k, ei.value)
+            blocks.limit = 10 ** 9  # allocations succeed again: the same context recovers
+            g = rhg.rhg_generate(c, p)
+            assert np.array_equal(rhg.rhg_graph_copy_edges(g), ref), "refusal %d" % k
+            rhg.rhg_graph_free(g)
+        finally:
+            rhg.rhg_ctx_destroy(c)
+        torch.cuda.synchronize()
+        assert not blocks.live, "refusal %d: %d blocks not returned" % (k, len(blocks.live))
+        assert blocks.unknown == 0, "refusal %d: unknown frees" % k
+
+
+def test_count_plan_survives_refused_output():
+    """rhg_count succeeds, the caller then has no room: rhg_emit refuses a short buffer and writes nothing."""
+    import torch
+    rhg.load()
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    try:
+        plan, m = rhg.rhg_count(c, rhg.params(20_000, 1.0, kbar=10, seed=2))
+        out = torch.full((2 * m,), -7, dtype=torch.int32, device="cuda")
+        with pytest.raises(rhg.RhgError) as ei:
+            rhg.rhg_emit(c, plan, out, m - 1)
+        assert ei.value.status == rhg.RHG_ETRUNC
+        torch.cuda.synchronize()
+        assert bool((out == -7).all())
+        rhg.rhg_emit(c, plan, out, m)
+        torch.cuda.synchronize()
+        e = out.view(-1, 2)
+        assert bool((e[:, 0] < e[:, 1]).all())
+        rhg.rhg_graph_free(plan)
+    finally:
+        rhg.rhg_ctx_destroy(c)
