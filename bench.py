@@ -157,6 +157,13 @@ def serving_requests(rhg, count, seed):
     return out
 
 
+def poisson_arrivals(count, rate, seed):
+    """Arrival times (s) of a Poisson process of the given rate, reproducible from its seed."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
 def _serve(rhg, srv, reqs, arrivals):
     """Submits reqs[i] at arrivals[i] seconds (None: all at once) from a
     submitter thread; collects in order.  Returns (wall s, latencies ms, edges)."""
@@ -197,8 +204,7 @@ def run_serving(args):
         T_sat, lat_sat, edges = _serve(rhg, srv, reqs, None)
         X = len(reqs) / T_sat
         lam = 0.7 * X
-        rng = np.random.default_rng(args.seed + 7)
-        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        arrivals = poisson_arrivals(len(reqs), lam, args.seed + 7)
         T, lat, edges2 = _serve(rhg, srv, reqs, arrivals)
         cnt = rhg.rhg_server_counters(srv)
     finally:

@@ -210,6 +210,12 @@ void rhg_graph_free(rhg_graph *g);
  * concurrently on several streams, small ones packed together into shared
  * launches; results are identical to rhg_generate's for the same params. */
 rhg_status rhg_server_create(int device, uint64_t mem_budget_bytes, rhg_server **out);
+/* Device memory a request is charged at admission (host only, no device use):
+ * its edge list, n * kbar / 2 pairs of 8 bytes with 25% headroom (kbar: the
+ * requested average degree, or for R-given requests the model's expected
+ * degree for that R, clamped to [1, n]), plus 256 bytes per point of work
+ * buffers and 1 MiB.  RHG_EINVAL for parameters rhg_generate would refuse. */
+rhg_status rhg_server_estimate_bytes(const rhg_params *params, uint64_t *bytes);
 /* Queue a request (params copied).  Returns at once with a ticket. */
 rhg_status rhg_server_submit(rhg_server *s, const rhg_params *params, uint64_t *ticket);
 /* Wait for a ticket: blocks until done (timeout_ms < 0), or waits at most

@@ -536,6 +536,7 @@ rhg_status rhgi::request_from_params(const rhg_params *p, Request &rq) {
     rq.precision = p->precision;
     rq.num_bands = p->num_bands;
     rq.band_ratio = p->band_ratio;
+    if (std::isnan(p->R) || std::isnan(p->kbar) || std::isnan(p->band_ratio)) return RHG_EINVAL;
     if (p->R > 0.0) {
         rq.R = p->R;
     } else {

@@ -108,6 +108,7 @@ def load(path: Optional[str] = None):
         "rhg_server_submit": (i32, [vp, P(rhg_params), P(u64)]),
         "rhg_server_wait": (i32, [vp, u64, i32, P(vp), P(d)]),
         "rhg_server_counters": (i32, [vp, P(rhg_server_stats)]),
+        "rhg_server_estimate_bytes": (i32, [P(rhg_params), P(u64)]),
         "rhg_server_destroy": (None, [vp]),
         "rhg_status_str": (ctypes.c_char_p, [i32]),
         "rhg_version": (ctypes.c_char_p, []),
@@ -312,6 +313,12 @@ def rhg_server_wait(s, ticket: int, timeout_ms: int = -1):
     _check(load().rhg_server_wait(s, int(ticket), int(timeout_ms), ctypes.byref(g), ctypes.byref(lat)),
            "rhg_server_wait")
     return g, lat.value
+
+
+def rhg_server_estimate_bytes(p: rhg_params) -> int:
+    b = ctypes.c_uint64()
+    _check(load().rhg_server_estimate_bytes(ctypes.byref(p), ctypes.byref(b)), "rhg_server_estimate_bytes")
+    return b.value
 
 
 def rhg_server_counters(s) -> dict:

@@ -97,3 +97,21 @@ def test_count_plan_survives_refused_output():
         rhg.rhg_graph_free(plan)
     finally:
         rhg.rhg_ctx_destroy(c)
+
+
+def test_short_host_buffer_refused():
+    """rhg_graph_copy_edges into a host buffer one pair short: RHG_ETRUNC, nothing copied."""
+    import ctypes
+    rhg.load()
+    c = rhg.rhg_ctx_create(0)
+    try:
+        g = rhg.rhg_generate(c, rhg.params(10_000, 1.0, kbar=10, seed=1))
+        m = rhg.rhg_graph_num_edges(g)
+        buf = np.full(2 * m, -3, dtype=np.int32)
+        st = rhg.load().rhg_graph_copy_edges(g, buf.ctypes.data_as(ctypes.c_void_p), m - 1)
+        assert st == rhg.RHG_ETRUNC and np.all(buf == -3)
+        e = rhg.rhg_graph_copy_edges(g)
+        assert len(e) == m
+        rhg.rhg_graph_free(g)
+    finally:
+        rhg.rhg_ctx_destroy(c)

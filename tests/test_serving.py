@@ -115,13 +115,13 @@ def test_served_small_request_vs_bruteforce(orc):
 
 
 def _est_bytes(n, kbar):
-    return int(n * max(kbar, 1.0) / 2.0 * 8.0 * 1.25) + n * 256 + (1 << 20)
+    return rhg.rhg_server_estimate_bytes(rhg.params(n, 1.0, kbar=kbar))
 
 
 def test_admission_budget(ctx):
     budget = 24 << 20
     reqs = [p for p in _mix(12, 40, n_lo=4000, n_hi=16384) if p.R <= 0]
-    assert len(reqs) >= 24 and max(_est_bytes(p.n, p.kbar) for p in reqs) < budget
+    assert len(reqs) >= 24 and max(rhg.rhg_server_estimate_bytes(p) for p in reqs) < budget
     srv = rhg.rhg_server_create(0, budget)
     try:
         tickets = [rhg.rhg_server_submit(srv, p) for p in reqs]
