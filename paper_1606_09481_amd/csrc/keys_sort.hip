@@ -9,6 +9,7 @@
 // of the exact angular interval, so the key resolution only affects how many
 // candidates are tested, never the edge set.
 #include <algorithm>
+#include <cmath>
 
 #include "rhg_kernels.h"
 
@@ -18,18 +19,42 @@ using namespace rhgd;
 struct BandsArg {
     int B;
     double c[MAX_BANDS + 1];
+    // Seeded points: the sampled radius r(u) = 2 asinh(sqrt(u) sinh(alpha R/2)) / alpha
+    // is increasing in the radius uniform u, so r >= c_i exactly when
+    // u >= ut[i] = (sinh(alpha c_i / 2) / sinh(alpha R / 2))^2.  The slab is read
+    // off ut without the transcendental; a u within UT_TOL (relative) of a
+    // threshold, where rounding could disagree, takes the radius itself.
+    double ut[MAX_BANDS + 1];
 };
+constexpr double UT_TOL = 1e-9;
 
 __global__ __launch_bounds__(256) void k_keys(Source src, BandsArg bands, uint32_t *keys, uint32_t *vals, int *err) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= src.n) return;
     double th, r;
-    load_point(src, i, th, r);
-    if (src.mode != SRC_SEED) {
-        if (!(th >= 0.0 && th <= TWO_PI && r >= 0.0 && r <= src.R)) atomicOr(err, 1);
-    }
     int b = 0;
-    while (b + 1 < bands.B && bands.c[b + 1] <= r) ++b;
+    if (src.mode == SRC_SEED) {
+        const uint64_t x1 = splitmix64(src.seed, 2ull * i);
+        const uint64_t x2 = splitmix64(src.seed, 2ull * i + 1ull);
+        th = (double)(x1 >> 11) * 0x1p-53 * TWO_PI;
+        const double u = (double)(x2 >> 11) * 0x1p-53;
+        // the boundaries are increasing: the slab is the number at or below u;
+        // the loop index is uniform, so each boundary is one scalar load
+        bool near = false;
+        for (int j = 1; j < bands.B; ++j) {
+            b += bands.ut[j] <= u ? 1 : 0;
+            near |= fabs(u - bands.ut[j]) <= UT_TOL * bands.ut[j];
+        }
+        if (near) {
+            sample_point(src, i, th, r);
+            b = 0;
+            for (int j = 1; j < bands.B; ++j) b += bands.c[j] <= r ? 1 : 0;
+        }
+    } else {
+        load_point(src, i, th, r);
+        if (!(th >= 0.0 && th <= TWO_PI && r >= 0.0 && r <= src.R)) atomicOr(err, 1);
+        for (int j = 1; j < bands.B; ++j) b += bands.c[j] <= r ? 1 : 0;
+    }
     keys[i] = ((uint32_t)b << QBITS) | qang(th);
     vals[i] = (uint32_t)i;
 }
@@ -37,7 +62,11 @@ __global__ __launch_bounds__(256) void k_keys(Source src, BandsArg bands, uint32
 void keys(const Source &src, int B, const double *c_host, uint32_t *k, uint32_t *v, int *err, hipStream_t st) {
     BandsArg ba;
     ba.B = B;
-    for (int j = 0; j <= B; ++j) ba.c[j] = c_host[j];
+    for (int j = 0; j <= B; ++j) {
+        ba.c[j] = c_host[j];
+        const double q = std::sinh(src.alpha * c_host[j] / 2.0) / src.sinh_half_aR;
+        ba.ut[j] = (src.mode == SRC_SEED && src.sinh_half_aR > 0.0) ? q * q : 0.0;
+    }
     (void)hipMemsetAsync(err, 0, sizeof(int), st);
     uint64_t blocks = (src.n + 255) / 256;
     if (blocks) hipLaunchKernelGGL(k_keys, dim3((unsigned)blocks), dim3(256), 0, st, src, ba, k, v, err);
@@ -329,14 +358,24 @@ void point_values(const Source &src, uint64_t n, double *th, double *rr, double 
 // (bucket(s-1), bucket(s)]; the tail kernel writes (bucket(last), 2^bits_j].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bucket(Geo g, uint32_t *btab) {
+    // per-slab layout in LDS (a point's slab is per lane: indexing the kernel
+    // arguments with it would be a vector load per field)
+    __shared__ uint32_t lbs[MAX_BANDS + 1], lbto[MAX_BANDS + 1];
+    __shared__ int lsh[MAX_BANDS + 1];
+    if (threadIdx.x <= (unsigned)g.B) {
+        lbs[threadIdx.x] = g.bs[threadIdx.x];
+        lbto[threadIdx.x] = g.bto[threadIdx.x];
+        lsh[threadIdx.x] = g.bshift[threadIdx.x];
+    }
+    __syncthreads();
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
     uint32_t key = g.keys[s];
     int j = (int)(key >> QBITS);
-    int sh = g.bshift[j];
+    int sh = lsh[j];
     int64_t b = (int64_t)((key & QMASK) >> sh);
-    int64_t bp = (s == g.bs[j]) ? -1 : (int64_t)((g.keys[s - 1] & QMASK) >> sh);
-    uint32_t *T = btab + g.bto[j];
+    int64_t bp = (s == lbs[j]) ? -1 : (int64_t)((g.keys[s - 1] & QMASK) >> sh);
+    uint32_t *T = btab + lbto[j];
     for (int64_t k = bp + 1; k <= b; ++k) T[k] = s;
 }
 
