@@ -5,7 +5,7 @@
 //   keys[n]   u32  (slab << 27) | q(theta): q is a monotone 27-bit
 //                  quantisation of the angle; the sort key and the search key
 //   idx[n]    u32  original point index of each sorted position
-//   th[n], rr[n]     f64 angle and radius
+//   th[n]            f64 angle
 //   epm[n]           f64x2 (exp(r), exp(-r))
 //   sh[n]            f64 sinh r
 //   hsc[n]           f64x2 (sin(theta/2), cos(theta/2))
@@ -66,7 +66,7 @@ struct Geo {
     uint32_t bto[MAX_BANDS + 1];  // bucket table offset of slab j
     int bshift[MAX_BANDS + 1];    // q >> bshift -> bucket
     const uint32_t *keys, *idx;
-    const double *th, *rr, *sh;
+    const double *th, *sh;
     const double2 *epm;  // (exp(r), exp(-r))
     const double2 *hsc;  // (sin(theta/2), cos(theta/2))
     const float4 *f32;   // (exp(r), exp(-r), sinh r, 0) rounded to FP32 (FP32 filter only)

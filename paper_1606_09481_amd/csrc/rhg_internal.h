@@ -14,7 +14,7 @@ namespace rhgi {
 
 enum Slot {
     S_KEYS, S_VALS, S_KEYS2, S_VALS2, S_HIST, S_SORTSCR,
-    S_TH, S_RR, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
+    S_TH, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
     S_COUNT
@@ -91,12 +91,12 @@ struct Graph {
 
 // Algorithmic HBM bytes of the timed path (sort through emit), the traffic
 // the method itself needs: per point the key and index written and read
-// once per sort digit pass, the table (7 x 8 B) written once and read by the
+// once per sort digit pass, the angle and table (6 x 8 B) written once and read by the
 // plan and by both query passes, per window 8 B written and read twice, per
 // edge one 8-byte pair written.
 inline uint64_t algorithmic_bytes(const Plan &p) {
     const uint64_t n = p.n;
-    const uint64_t per_point = 8ull * 2 * 4 + 56 + 5 * 8 * 3;
+    const uint64_t per_point = 8ull * 2 * 4 + 48 + 5 * 8 * 3;
     return n * per_point + p.windows * 8 * 3 + p.m * 8;
 }
 

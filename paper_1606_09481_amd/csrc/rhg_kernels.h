@@ -27,9 +27,9 @@ size_t sort_scratch_bytes(uint64_t n);
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                 int bits, hipStream_t st);
 
-// a1 + a3 gather: per sorted position, the point's angle, radius and table
+// a1 + a3 gather: per sorted position, the point's angle and table
 // (computed, or copied from the caller's table) in sorted order.
-void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double *rr, double2 *epm,
+void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double2 *epm,
             double *sh, double2 *hsc, float4 *f32, hipStream_t st);
 
 // Same values in original order (for exporting the exact bits used).
@@ -94,7 +94,7 @@ struct SmallDesc {
     rhgd::Geo geo;
     int fp32, key_bits;
     uint32_t *keys, *vals, *keys2, *vals2;
-    double *th, *rr, *sh;
+    double *th, *sh;
     double2 *epm, *hsc;
     float4 *f32;
     uint32_t *btab;

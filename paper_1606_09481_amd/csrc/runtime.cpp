@@ -353,7 +353,6 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
 
     // table in sorted order (needs no layout)
     RHG_BUF(th, double, S_TH, n);
-    RHG_BUF(rr, double, S_RR, n);
     RHG_BUF(epm, double2, S_EP, n);
     RHG_BUF(sh, double, S_SH, n);
     RHG_BUF(hsc, double2, S_HS, n);
@@ -362,7 +361,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         f32 = (float4 *)c->buf(S_EP32, sizeof(float4) * n);
         if (!f32) return RHG_ENOMEM;
     }
-    rhgk::gather(src, vals, n, th, rr, epm, sh, hsc, f32, st);
+    rhgk::gather(src, vals, n, th, epm, sh, hsc, f32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
 
     // slab sizes -> layout of windows and bucket index
@@ -397,7 +396,6 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.keys = keys;
     g.idx = vals;
     g.th = th;
-    g.rr = rr;
     g.epm = epm;
     g.sh = sh;
     g.hsc = hsc;

@@ -223,7 +223,6 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         sA.geo.keys = D.keys;
         sA.geo.idx = D.vals;
         sA.geo.th = D.th;
-        sA.geo.rr = D.rr;
         sA.geo.sh = D.sh;
         sA.geo.epm = D.epm;
         sA.geo.hsc = D.hsc;
@@ -246,7 +245,6 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         load_point(D.src, v, th, r);
         point_table(D.src, v, th, r, a, b, c, d, e);
         D.th[s] = th;
-        D.rr[s] = r;
         D.epm[s] = make_double2(a, b);
         D.sh[s] = c;
         D.hsc[s] = make_double2(d, e);
