@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t unit = exec_unit(A, w);
     if (unit == ~0ull) return;
-    emit_unit<WIDE>(A, unit, lane, sm[w]);
+    emit_unit<WIDE, true>(A, unit, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {

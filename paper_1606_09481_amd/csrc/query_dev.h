@@ -582,10 +582,16 @@ struct EmitWalk {
     bool ne, in_seg;
 };
 
-template <bool WIDE>
+// Decision words of a unit read with scalar loads through the constant
+// address space: only where the bitmap was written by an earlier kernel (the
+// scalar cache is invalidated at each dispatch); within one kernel the words
+// go through LDS instead.
+typedef const __attribute__((address_space(4))) unsigned long long *const_words_t;
+
+template <bool WIDE, bool SBITS>
 __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup &u, uint32_t myqi, uint32_t todo,
-                                             int lane, uint64_t le, uint64_t lt, EmitSmem &S, EmitWalk &w,
-                                             EmitStep &s) {
+                                             int lane, uint64_t le, uint64_t lt, EmitSmem &S, const_words_t cw,
+                                             EmitWalk &w, EmitStep &s) {
     constexpr int VT = VT_EMIT;
     const Geo &g = A.geo;
     s.valid = false;
@@ -620,10 +626,16 @@ __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup
 #pragma unroll
     for (int i = 0; i < VT; ++i) {
         // decision word of the sub-round (uniform: scalar registers)
-        uint64_t x = S.bits[w.word + i];
-        x = (w.t0 + 64u * i < w.e) ? x : 0ull;
-        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+        uint64_t m;
+        if (SBITS) {
+            const uint32_t wi = w.word + i < (uint32_t)BITW ? w.word + i : (uint32_t)BITW - 1u;
+            m = (w.t0 + 64u * i < w.e) ? cw[wi] : 0ull;
+        } else {
+            uint64_t x = S.bits[w.word + i];
+            x = (w.t0 + 64u * i < w.e) ? x : 0ull;
+            m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+        }
         const uint32_t rk = (w.base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
         w.base += (uint32_t)__popcll(M[i]);
         const bool mine = (m >> lane) & 1ull;
@@ -649,14 +661,16 @@ __device__ __forceinline__ void emit_store(const EmitStep &s, __amdgpu_buffer_rs
     }
 }
 
-template <bool WIDE>
+template <bool WIDE, bool SBITS = false>
 __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int lane, EmitSmem &S) {
     const Geo &g = A.geo;
     const uint32_t todo = uniform_u32(A.unit_edges[unit]);
     if (todo == 0) return;
     const UnitSetup u = unit_setup(A, unit, lane);
     const uint32_t myqi = u.valid ? g.idx[u.v] : 0u;
-    for (int k = lane; k < BITW + VT_EMIT; k += 64) S.bits[k] = k < BITW ? A.bits[unit * BITW + k] : 0ull;
+    const_words_t cw = (const_words_t)(A.bits + uniform_u64(unit) * BITW);
+    if (!SBITS)
+        for (int k = lane; k < BITW + VT_EMIT; k += 64) S.bits[k] = k < BITW ? A.bits[unit * BITW + k] : 0ull;
 #pragma unroll
     for (int i = 0; i < VT_EMIT; ++i) S.flag[i * 64 + lane] = 0u;
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
@@ -674,12 +688,12 @@ __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int
     w.t0 = w.e = w.base = w.word = w.be = w.nj = w.excl = w.out_rel = 0u;
     w.ne = w.in_seg = false;
     EmitStep s0, s1;
-    emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s0);
+    emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s0);
     while (s0.valid) {
-        emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s1);  // gathers of the next step ...
+        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s1);  // gathers of the next step ...
         emit_store(s0, out);                                            // ... in flight over these stores
         if (!s1.valid) break;
-        emit_prepare<WIDE>(A, u, myqi, todo, lane, le, lt, S, w, s0);
+        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s0);
         emit_store(s1, out);
     }
 }
