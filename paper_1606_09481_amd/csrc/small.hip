@@ -14,7 +14,7 @@
 namespace rhgk {
 using namespace rhgd;
 
-constexpr int SM_THREADS = 512;
+constexpr int SM_THREADS = 1024;
 constexpr int SM_WAVES = SM_THREADS / 64;
 constexpr int SM_ITEMS = 16;
 constexpr int SM_TILE = SM_THREADS * SM_ITEMS;  // keys ranked per sort step
