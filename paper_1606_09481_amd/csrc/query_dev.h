@@ -157,6 +157,7 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
     uint64_t *row = batch_slab_off + (uint64_t)b * (g.B + 1);
     for (int j = lane; j <= jmin && j <= g.B; j += 64) row[j] = 0;
     uint64_t acc = 0;
+    const bool small = 64ull * g.n < (1ull << 32);
     for (int j = jmin; j < g.B; ++j) {
         uint32_t cnt = 0;
         if (valid && j >= i) {
@@ -164,7 +165,9 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
             win[g.winbase[j] + s] = x;
             cnt = x.y;
         }
-        acc += wave_sum_u64(cnt);
+        // 64 window counts of at most n each: a 32-bit DPP sum (no LDS
+        // round trips) whenever 64 n < 2^32, else the 64-bit shuffle sum
+        acc += small ? (uint64_t)wave_bcast_u32(wave_incl_scan_u32(cnt), 63) : wave_sum_u64(cnt);
         if (lane == 0) row[j + 1] = acc;
     }
     if (lane == 0) batch_cand[b] = acc;
