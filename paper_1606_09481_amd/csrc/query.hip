@@ -102,7 +102,8 @@ void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_t
 template <int FP32, bool WIDE>
 __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
     __shared__ CountSmem<FP32> sm[4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wavefront index in scalar registers: the unit lookups become scalar loads
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const uint64_t unit = exec_unit(A, w);
     if (unit == ~0ull) return;  // uniform per wavefront; no block-wide barriers below
     count_unit<FP32, WIDE>(A, unit, lane, sm[w]);
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     __shared__ EmitSmem sm[4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const uint64_t unit = exec_unit(A, w);
     if (unit == ~0ull) return;
     emit_unit<WIDE, true>(A, unit, lane, sm[w]);  // bitmaps from the count kernel: scalar loads

@@ -624,26 +624,42 @@ __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup
         w.t0 = a;
         w.in_seg = a < w.e;
     }
-    uint64_t M[VT];
-    step_starts<VT>(S.flag, lane, w.ne, w.excl, w.t0, M);
+    // The step's VT decision words (uniform: scalar registers), read
+    // unconditionally as one run (the bitmap carries VT words of padding past
+    // its last unit; words past the segment end are masked), so that one wait
+    // covers them all instead of one per sub-round.
+    uint64_t mw[VT];
 #pragma unroll
     for (int i = 0; i < VT; ++i) {
-        // decision word of the sub-round (uniform: scalar registers)
-        uint64_t m;
         if (SBITS) {
-            const uint32_t wi = w.word + i < (uint32_t)BITW ? w.word + i : (uint32_t)BITW - 1u;
-            m = (w.t0 + 64u * i < w.e) ? cw[wi] : 0ull;
+            mw[i] = cw[w.word + i];
         } else {
-            uint64_t x = S.bits[w.word + i];
-            x = (w.t0 + 64u * i < w.e) ? x : 0ull;
-            m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
-                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+            const uint64_t x = S.bits[w.word + i];
+            mw[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
         }
-        const uint32_t rk = (w.base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
+    }
+    uint64_t M[VT];
+    step_starts<VT>(S.flag, lane, w.ne, w.excl, w.t0, M);
+    // ranks first, then every LDS read of the step, then positions and gathers:
+    // no read sits behind a branch, so the reads of all sub-rounds share one wait
+    uint32_t rk[VT], pb[VT];
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        rk[i] = (w.base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
         w.base += (uint32_t)__popcll(M[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        pb[i] = S.pb[rk[i]];
+        s.qi[i] = S.qi[rk[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        const uint64_t m = (w.t0 + 64u * i < w.e) ? mw[i] : 0ull;
         const bool mine = (m >> lane) & 1ull;
-        const uint32_t p = mine ? position_pb(S.pb[rk], w.t0 + 64u * i + lane, w.be, w.nj) : w.be - 1u;
-        s.qi[i] = S.qi[rk];
+        const uint32_t pp = position_pb(pb[i], w.t0 + 64u * i + lane, w.be, w.nj);
+        const uint32_t p = mine ? pp : w.be - 1u;
         s.wi[i] = ld<WIDE>(g.idx, p);
         s.off[i] = mine ? (w.out_rel + (uint32_t)__popcll(m & lt)) * 8u : NO_STORE;
         w.out_rel += (uint32_t)__popcll(m);

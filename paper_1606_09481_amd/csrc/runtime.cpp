@@ -430,7 +430,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(U, 1));
     RHG_BUF(ueoff, uint64_t, S_UEOFF, U + 1);
     RHG_BUF(stats, unsigned long long, S_STATS, 4);
-    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * BITMAP_WORDS);
+    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * BITMAP_WORDS + 8);  // + the emit's read-ahead
     void *scan2 = c->buf(S_SCANSCR2, rhgk::scan_scratch_bytes(std::max<uint64_t>(U, 1)));
     if (!scan2) return RHG_ENOMEM;
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT0], st));  // count phase: unit bookkeeping + order + count
