@@ -118,6 +118,7 @@ constexpr int S_TILE = S_THREADS * S_ITEMS;
 constexpr int S_MAX_PASSES = 4;
 constexpr uint64_t ST_LOCAL = 1ull << 62, ST_TOTAL = 2ull << 62, ST_VALUE = (1ull << 62) - 1;
 constexpr uint32_t SORT_SPIN_LIMIT = 1u << 22;
+constexpr int S_LOOK = 4;  // look-back: status words read per round trip
 
 // Scratch layout: [tickets (S_MAX_PASSES u32) | error u32 | pad] [digit counts S_MAX_PASSES x 256 u32]
 //                 [status S_MAX_PASSES x ntiles x 256 u64]
@@ -140,16 +141,33 @@ static SortScratch sort_scratch(void *scratch, uint32_t ntiles) {
 
 __global__ __launch_bounds__(S_THREADS) void k_digit_counts(const uint32_t *keys, uint32_t n, int passes,
                                                             uint32_t *counts) {
-    __shared__ uint32_t h[S_MAX_PASSES][256];
-    for (int q = 0; q < S_MAX_PASSES; ++q) h[q][threadIdx.x] = 0;
+    __shared__ uint32_t h[4][S_MAX_PASSES][256];
+    const int w = threadIdx.x >> 6;
+    for (int q = 0; q < S_MAX_PASSES; ++q)
+        for (int x = 0; x < 4; ++x) h[x][q][threadIdx.x] = 0;
     __syncthreads();
-    for (uint32_t i = blockIdx.x * S_THREADS + threadIdx.x; i < n; i += gridDim.x * S_THREADS) {
+    // 16-byte loads where the keys are 16-byte aligned (every buffer here is);
+    // otherwise the scalar tail below takes all of them
+    const uint32_t n4 = ((uintptr_t)keys & 15u) == 0 ? n / 4 : 0u;
+    const uint4 *k4 = (const uint4 *)keys;
+    for (uint32_t i = blockIdx.x * S_THREADS + threadIdx.x; i < n4; i += gridDim.x * S_THREADS) {
+        const uint4 k = k4[i];
+        for (int q = 0; q < passes; ++q) {
+            atomicAdd(&h[w][q][(k.x >> (8 * q)) & 255u], 1u);
+            atomicAdd(&h[w][q][(k.y >> (8 * q)) & 255u], 1u);
+            atomicAdd(&h[w][q][(k.z >> (8 * q)) & 255u], 1u);
+            atomicAdd(&h[w][q][(k.w >> (8 * q)) & 255u], 1u);
+        }
+    }
+    for (uint32_t i = 4 * n4 + blockIdx.x * S_THREADS + threadIdx.x; i < n; i += gridDim.x * S_THREADS) {
         const uint32_t k = keys[i];
-        for (int q = 0; q < passes; ++q) atomicAdd(&h[q][(k >> (8 * q)) & 255u], 1u);
+        for (int q = 0; q < passes; ++q) atomicAdd(&h[w][q][(k >> (8 * q)) & 255u], 1u);
     }
     __syncthreads();
-    for (int q = 0; q < passes; ++q)
-        if (h[q][threadIdx.x]) atomicAdd(&counts[q * 256 + threadIdx.x], h[q][threadIdx.x]);
+    for (int q = 0; q < passes; ++q) {
+        const uint32_t t = h[0][q][threadIdx.x] + h[1][q][threadIdx.x] + h[2][q][threadIdx.x] + h[3][q][threadIdx.x];
+        if (t) atomicAdd(&counts[q * 256 + threadIdx.x], t);
+    }
 }
 
 // Exclusive scan of 256 values, one per thread of the workgroup (4 wavefronts).
@@ -219,22 +237,38 @@ __global__ __launch_bounds__(S_THREADS) void k_sort_pass(const uint32_t *keys, c
     const uint32_t gd = block_excl_256(counts[d], wtot);
     uint64_t before = 0;
     if (tile > 0) {
-        uint32_t k2 = tile - 1, spins = 0;
+        // S_LOOK predecessors per round trip (tile k2 and the ones below it),
+        // taken in order: LOCAL counts are added, the first TOTAL ends the
+        // walk, an unpublished word is read again on the next round
+        int k2 = (int)tile - 1;
+        uint32_t spins = 0;
         for (;;) {
-            const uint64_t st = __hip_atomic_load(status + (uint64_t)k2 * 256 + d, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = st & ~ST_VALUE;
-            if (flag == 0) {
+            uint64_t sw[S_LOOK];
+#pragma unroll
+            for (int q = 0; q < S_LOOK; ++q) {
+                const int t = k2 - q > 0 ? k2 - q : 0;  // tile 0 is TOTAL: the walk never passes it
+                sw[q] = __hip_atomic_load(status + (uint64_t)t * 256 + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            int q = 0;
+            bool done = false;
+            for (; q < S_LOOK; ++q) {
+                const uint64_t flag = sw[q] & ~ST_VALUE;
+                if (flag == 0) break;
+                before += sw[q] & ST_VALUE;
+                if (flag == ST_TOTAL || k2 - q == 0) {
+                    done = true;
+                    break;
+                }
+            }
+            if (done) break;
+            k2 -= q;
+            if (q == 0) {
                 if (++spins > SORT_SPIN_LIMIT) {
                     atomicOr(error, 1u);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                continue;
             }
-            before += st & ST_VALUE;
-            if (flag == ST_TOTAL || k2 == 0) break;
-            --k2;
         }
         __hip_atomic_store(my, ST_TOTAL | (before + h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -285,7 +319,8 @@ void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *va
     const size_t status_bytes = (size_t)passes * ntiles * 256 * sizeof(uint64_t);
     // tickets, error flag, digit counts and the status words of every pass start at zero
     (void)hipMemsetAsync(scratch, 0, 256 + S_MAX_PASSES * 256 * sizeof(uint32_t) + status_bytes, st);
-    const unsigned cblocks = (unsigned)std::min<uint64_t>(1024, (n + S_THREADS * 16 - 1) / (S_THREADS * 16));
+    // few workgroups: each adds its 4 x 256 counts to the same global words
+    const unsigned cblocks = (unsigned)std::min<uint64_t>(256, (n + S_THREADS * 16 - 1) / (S_THREADS * 16));
     hipLaunchKernelGGL(k_digit_counts, dim3(cblocks), dim3(S_THREADS), 0, st, keys, (uint32_t)n, passes, x.counts);
     uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
     for (int p = 0; p < passes; ++p) {
