@@ -70,32 +70,48 @@ static unsigned exec_blocks(uint64_t U) {
 }
 
 // Sector key of each unit: the top bits of the quantised angle of its first candidate.
+// Each wavefront keys UKEY_UPW units: their chains of dependent loads (unit,
+// batch, slab offsets, window, key) are interleaved, so that several are in
+// flight at once.
+constexpr int UKEY_UPW = 2;
 __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, uint32_t *id) {
     const Geo &g = A.geo;
     const int lane = threadIdx.x & 63;
-    const uint64_t unit = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (unit >= A.n_units) return;
-    const UnitSetup u = unit_setup(A, unit, lane);
-    uint32_t st, cnt, excl, tot;
-    slab_windows(g, A, u, u.jstart, st, cnt, excl, tot);
-    const uint32_t off = (uint32_t)(u.r0 > u.pos ? u.r0 - u.pos : 0);
-    const bool here = cnt != 0u && excl <= off && off - excl < cnt;
-    const uint64_t m = __ballot(here);
-    const int l = m ? __ffsll((long long)m) - 1 : 0;
-    const uint32_t be = g.bs[u.jstart + 1], nj = be - g.bs[u.jstart];
-    uint32_t p = g.bs[u.jstart];
-    if (lane == l && m) p = position_of(make_uint2(st, excl), off, be, nj);
-    p = wave_bcast_u32(p, l);
-    if (lane == 0) {
-        key[unit] = (g.keys[p] & QMASK) >> (QBITS - SECTOR_BITS);
-        id[unit] = (uint32_t)unit;
+    const uint64_t unit0 = ((uint64_t)blockIdx.x * 4 + (uint64_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) * UKEY_UPW;
+    UnitSetup u[UKEY_UPW];
+    uint32_t st[UKEY_UPW], cnt[UKEY_UPW], excl[UKEY_UPW], tot[UKEY_UPW], p[UKEY_UPW];
+#pragma unroll
+    for (int q = 0; q < UKEY_UPW; ++q) {
+        const uint64_t unit = unit0 + q < A.n_units ? unit0 + q : A.n_units - 1;
+        u[q] = unit_setup(A, unit, lane);
+    }
+#pragma unroll
+    for (int q = 0; q < UKEY_UPW; ++q) slab_windows(g, A, u[q], u[q].jstart, st[q], cnt[q], excl[q], tot[q]);
+#pragma unroll
+    for (int q = 0; q < UKEY_UPW; ++q) {
+        const uint32_t off = (uint32_t)(u[q].r0 > u[q].pos ? u[q].r0 - u[q].pos : 0);
+        const bool here = cnt[q] != 0u && excl[q] <= off && off - excl[q] < cnt[q];
+        const uint64_t m = __ballot(here);
+        const int l = m ? __ffsll((long long)m) - 1 : 0;
+        const uint32_t be = g.bs[u[q].jstart + 1], nj = be - g.bs[u[q].jstart];
+        uint32_t pp = g.bs[u[q].jstart];
+        if (lane == l && m) pp = position_of(make_uint2(st[q], excl[q]), off, be, nj);
+        p[q] = wave_bcast_u32(pp, l);
+    }
+#pragma unroll
+    for (int q = 0; q < UKEY_UPW; ++q) {
+        const uint32_t kq = (g.keys[p[q]] & QMASK) >> (QBITS - SECTOR_BITS);
+        if (lane == 0 && unit0 + q < A.n_units) {
+            key[unit0 + q] = kq;
+            id[unit0 + q] = (uint32_t)(unit0 + q);
+        }
     }
 }
 
 void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_tmp, uint32_t *id_tmp,
                 void *sort_scratch, hipStream_t st) {
     if (!a.n_units) return;
-    hipLaunchKernelGGL(k_unit_key, dim3((unsigned)((a.n_units + 3) / 4)), dim3(256), 0, st, a, key, id);
+    hipLaunchKernelGGL(k_unit_key, dim3((unsigned)((a.n_units + 4 * UKEY_UPW - 1) / (4 * UKEY_UPW))), dim3(256), 0, st, a, key, id);
     radix_sort(key, id, key_tmp, id_tmp, sort_scratch, a.n_units, SECTOR_BITS, st);
 }
 

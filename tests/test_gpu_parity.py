@@ -129,7 +129,15 @@ def test_seeded_points_match_oracle_sampler(ctx, orc, n, alpha, kbar, seed):
     R = orc.target_radius(n, alpha, kbar)
     g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=seed))
     th, r, t, K = rhg.rhg_graph_copy_points(g)
+    windows = rhg.rhg_graph_stats(g)["windows"]
     rhg.rhg_graph_free(g)
+    # every point sits in the slab its own radius defines (Sec. III-A): the
+    # device takes the slab from thresholds on the radius uniform, so check it
+    # through the window count, sum over points of (B - slab)
+    B = orc.default_bands(n)
+    c = rhg.rhg_band_boundaries(R, B, 0.9)
+    slab = np.searchsorted(c[1:B], r, side="right")
+    assert windows == int(np.sum(B - slab))
     tho, ro = orc.sample(n, alpha, R, seed)
     assert np.array_equal(th, tho)                     # one rounding, identical on both sides
     assert _ulps(r, ro).max() <= 4                     # device asinh vs host asinh
