@@ -99,6 +99,54 @@ def run_gpu(args):
     return res
 
 
+def run_shares(args):
+    """One GPU's share of an S-GPU run of the same workload: the whole table is
+    sampled, sorted and planned, count and emit cover the batches of share k
+    (cut on the plan's candidate prefix).  Host-timed like the main step."""
+    import torch
+    from paper_1606_09481_amd import rhg
+
+    S = args.shares
+    rhg.load()
+    torch.cuda.set_device(0)
+    ctx = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    rhg.rhg_ctx_set_option(ctx, rhg.RHG_OPT_SHARD_COUNT, S)
+    p = rhg.params(args.n, args.alpha, kbar=args.kbar, seed=args.seed)
+    out, per = None, []
+    try:
+        for k in range(S):
+            rhg.rhg_ctx_set_option(ctx, rhg.RHG_OPT_SHARD_INDEX, k)
+            times = []
+            for it in range(1 + 2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan, m = rhg.rhg_count(ctx, p)
+                if out is None or out.numel() < 2 * m:
+                    rhg.rhg_graph_free(plan)
+                    out = None
+                    torch.cuda.synchronize()
+                    out = torch.empty(2 * m + 1024, dtype=torch.int32, device="cuda")
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    plan, m = rhg.rhg_count(ctx, p)
+                rhg.rhg_emit(ctx, plan, out, out.numel() // 2)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = rhg.rhg_graph_stats(plan)
+                rhg.rhg_graph_free(plan)
+                if it >= 1:
+                    times.append(t1 - t0)
+            per.append({"edges": m, "candidates": st["candidates"], "ms": 1e3 * sum(times) / len(times),
+                        "count_ms": st["ms"][4], "emit_ms": st["ms"][6]})
+            print("[bench] share %d/%d: %.3f ms, m=%d" % (k, S, per[-1]["ms"], m), file=sys.stderr, flush=True)
+    finally:
+        rhg.rhg_ctx_destroy(ctx)
+        del out
+    return {"count": S, "what": "whole table sampled, sorted and planned; count and emit for 1/%d of the "
+                                "queries (by candidates)" % S,
+            "max_ms": max(x["ms"] for x in per), "mean_ms": sum(x["ms"] for x in per) / S, "shares": per}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_traffic_n1e7_a075_k100.md")
 KERNEL_SOURCES = ["query_dev.h", "query.hip", "rhg_device.h", "rhg_kernels.h"]
 
@@ -273,10 +321,12 @@ def main():
                          "scales HBM byte counters under rocprofv3 --pmc)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--shares", type=int, default=8,
+                    help="also time each of this many one-GPU query shares (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this generator runs on one GPU; multi-GPU sharding is not built (see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py: runs on one GPU only; the 'share' object of its JSON line times one GPU's share "
+              "of a multi-GPU run (no collectives are built)", file=sys.stderr)
         sys.exit(2)
 
     if args.serve_only:
@@ -313,6 +363,8 @@ def main():
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
         "roofline": roof,
     }
+    if args.shares > 1:
+        line["share"] = run_shares(args)
     if not args.no_serve:
         line["serving"] = run_serving(args)
     if not args.no_cpu:

@@ -126,8 +126,18 @@ rhg_status rhg_ctx_set_allocator(rhg_ctx *ctx, void *(*alloc)(size_t, void *), v
  *   RHG_OPT_FP32_EXHAUSTIVE (value 0/1): in RHG_FP32_RECHECK count passes also
  *   evaluate the FP64 test on every candidate the filter decided and count
  *   disagreements into rhg_stats.disagreements (a self-check of the margin;
- *   slower). */
-typedef enum { RHG_OPT_FP32_EXHAUSTIVE = 1 } rhg_option;
+ *   slower).
+ *   RHG_OPT_SHARD_COUNT (S, 1..65536, default 1) and RHG_OPT_SHARD_INDEX
+ *   (k, 0..S-1, default 0): one share of the query side of Alg. 1, as one of
+ *   S devices would run it.  Every point is still sampled, sorted and planned
+ *   (the whole table), but only the queries of shard k are counted and
+ *   emitted: a contiguous range of 64-query batches of the sorted order, cut
+ *   where the running candidate total crosses k/S and (k+1)/S of the whole.
+ *   Each edge is found by exactly one query, so the S shards' edge lists are
+ *   disjoint and together are the whole graph.  rhg_stats.edges and
+ *   .candidates then count the shard only.  A generation with k >= S returns
+ *   RHG_EINVAL.  The serving path ignores these options. */
+typedef enum { RHG_OPT_FP32_EXHAUSTIVE = 1, RHG_OPT_SHARD_COUNT = 2, RHG_OPT_SHARD_INDEX = 3 } rhg_option;
 rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value);
 
 /* Release the context and its work buffers (graphs stay valid). */

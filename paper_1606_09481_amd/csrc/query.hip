@@ -61,7 +61,7 @@ __device__ __forceinline__ uint64_t exec_unit(const QueryArgs &A, int w) {
     const uint64_t x = blockIdx.x % NXCD, slot = (uint64_t)(blockIdx.x / NXCD) * 4 + w;
     const uint64_t k = x * chunk + slot;
     if (slot >= chunk || k >= U) return ~0ull;
-    return A.unit_order ? A.unit_order[k] : k;
+    return A.unit_order ? A.unit_order[k] : A.unit_base + k;
 }
 
 static unsigned exec_blocks(uint64_t U) {
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) {
         const uint64_t unit = unit0 + q < A.n_units ? unit0 + q : A.n_units - 1;
-        u[q] = unit_setup(A, unit, lane);
+        u[q] = unit_setup(A, A.unit_base + unit, lane);
     }
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) slab_windows(g, A, u[q], u[q].jstart, st[q], cnt[q], excl[q], tot[q]);
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
         const uint32_t kq = (g.keys[p[q]] & QMASK) >> (QBITS - SECTOR_BITS);
         if (lane == 0 && unit0 + q < A.n_units) {
             key[unit0 + q] = kq;
-            id[unit0 + q] = (uint32_t)(unit0 + q);
+            id[unit0 + q] = (uint32_t)(A.unit_base + unit0 + q);
         }
     }
 }

@@ -53,6 +53,11 @@ void units_per_batch(const uint64_t *batch_cand, uint64_t nb, uint64_t *nunits, 
 // units per batch (nunits: nb scratch, used above one workgroup's size).
 void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nunits, uint64_t *uoff, void *scratch,
                 hipStream_t st);
+// Query share k of S: out = {b0, b1, u0, u1, c0, c1}, the batch range [b0, b1)
+// cut where the candidate prefix boff crosses k/S and (k+1)/S of the total,
+// its unit range (uoff) and candidate range (boff).  One thread.
+void shard_cut(const uint64_t *boff, const uint64_t *uoff, uint64_t nb, uint32_t S, uint32_t k, uint64_t *out,
+               hipStream_t st);
 void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units, uint32_t *unit_batch,
                      hipStream_t st);
 
@@ -67,7 +72,8 @@ struct QueryArgs {
     const uint64_t *unit_off;   // per batch, first unit (exclusive scan of units)
     const uint32_t *unit_batch;
     const uint32_t *unit_order;    // execution order of units (sector-sorted), or null
-    uint64_t n_units;
+    uint64_t n_units;              // units executed: global ids unit_base .. unit_base + n_units - 1
+    uint64_t unit_base;            // (a query share runs a contiguous range of the units)
     uint32_t *unit_edges;          // count: edges per unit
     unsigned long long *bits;      // count -> emit: BITMAP_WORDS words of decisions per unit
     const uint64_t *unit_edge_off; // emit

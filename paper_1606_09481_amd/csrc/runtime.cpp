@@ -216,6 +216,16 @@ extern "C" rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value
         c->exhaustive = value ? 1 : 0;
         return RHG_OK;
     }
+    if (option == RHG_OPT_SHARD_COUNT) {
+        if (value < 1 || value > 65536) return RHG_EINVAL;
+        c->shard_count = (uint32_t)value;
+        return RHG_OK;
+    }
+    if (option == RHG_OPT_SHARD_INDEX) {
+        if (value < 0 || value >= 65536) return RHG_EINVAL;
+        c->shard_index = (uint32_t)value;
+        return RHG_OK;
+    }
     return RHG_EINVAL;
 }
 
@@ -316,6 +326,8 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     const hipStream_t st = c->stream;
     const uint64_t n = pl.n;
     const int B = pl.B;
+    const uint32_t S = c->shard_count, K = c->shard_index;
+    if (K >= S) return RHG_EINVAL;  // query share out of range
     c->generation++;
     pl.generation = c->generation;
 
@@ -416,25 +428,41 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     if (!scan_scr) return RHG_ENOMEM;
     rhgk::plan(g, win, bcand, bsoff, st);
     rhgk::plan_scans(bcand, nb, boff, nunits, uoff, scan_scr, st);
+    // a query share: its batch range, cut on the candidate prefix (whole table planned)
+    uint64_t *shard = nullptr;
+    if (S > 1) {
+        shard = (uint64_t *)c->buf(S_SHARD, 8 * sizeof(uint64_t));
+        if (!shard) return RHG_ENOMEM;
+        rhgk::shard_cut(boff, uoff, nb, S, K, shard, st);
+    }
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN1], st));
     uint64_t *pin = (uint64_t *)c->pinned;
     RHG_HIP(hipMemcpyAsync(pin + 0, boff + nb, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipMemcpyAsync(pin + 1, uoff + nb, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    if (shard) RHG_HIP(hipMemcpyAsync(pin + 16, shard, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipStreamSynchronize(st));
+    const uint64_t Uall = pin[1];
+    if (Uall >= (1ull << 31)) return RHG_ERANGE;
+    uint64_t u0 = 0, U = Uall;  // units of this share: global ids u0 .. u0 + U - 1
     pl.candidates = pin[0];
-    const uint64_t U = pin[1];
-    if (U >= (1ull << 31)) return RHG_ERANGE;
+    if (shard) {
+        if (pin[18] > pin[19] || pin[19] > Uall || pin[20] > pin[21]) return RHG_EDEVICE;
+        u0 = pin[18];
+        U = pin[19] - pin[18];
+        pl.candidates = pin[21] - pin[20];
+    }
     pl.n_units = U;
 
-    RHG_BUF(ubatch, uint32_t, S_UBATCH, std::max<uint64_t>(U, 1));
-    RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(U, 1));
-    RHG_BUF(ueoff, uint64_t, S_UEOFF, U + 1);
+    // per-unit arrays are indexed by global unit id (a share touches its range only)
+    RHG_BUF(ubatch, uint32_t, S_UBATCH, std::max<uint64_t>(Uall, 1));
+    RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(Uall, 1));
+    RHG_BUF(ueoff, uint64_t, S_UEOFF, Uall + 1);
     RHG_BUF(stats, unsigned long long, S_STATS, 4);
-    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(U, 1) * BITMAP_WORDS + 8);  // + the emit's read-ahead
+    RHG_BUF(bits, unsigned long long, S_BITS, std::max<uint64_t>(Uall, 1) * BITMAP_WORDS + 8);  // + the emit's read-ahead
     void *scan2 = c->buf(S_SCANSCR2, rhgk::scan_scratch_bytes(std::max<uint64_t>(U, 1)));
     if (!scan2) return RHG_ENOMEM;
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT0], st));  // count phase: unit bookkeeping + order + count
-    rhgk::unit_batch_fill(uoff, nb, U, ubatch, st);
+    rhgk::unit_batch_fill(uoff, nb, Uall, ubatch, st);
     RHG_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, st));
 
     rhgk::QueryArgs &qa = pl.qa;
@@ -446,6 +474,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.unit_off = uoff;
     qa.unit_batch = ubatch;
     qa.n_units = U;
+    qa.unit_base = u0;
     qa.unit_edges = uedges;
     qa.bits = bits;
     qa.unit_edge_off = ueoff;
@@ -467,9 +496,10 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipEventRecord(c->ev[EV_QCOUNT0], st));
     rhgk::query_count(qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
-    rhgk::scan_u32(uedges, ueoff, U, scan2, st);
+    // edge offsets of the share's units, from 0 at its first unit
+    rhgk::scan_u32(uedges + u0, ueoff + u0, U, scan2, st);
     RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
-    RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + u0 + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     uint32_t *usort_err = (uint32_t *)((char *)c->pinned + 1028);
     *usort_err = 0;

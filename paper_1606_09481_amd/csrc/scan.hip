@@ -229,6 +229,37 @@ void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nun
 
 // unit_off[b] .. unit_off[b+1]-1 are the units of batch b: unit u belongs to
 // the last batch b with unit_off[b] <= u.
+__global__ void k_shard_cut(const uint64_t *boff, const uint64_t *uoff, uint64_t nb, uint32_t S, uint32_t k,
+                            uint64_t *out) {
+    if (threadIdx.x != 0) return;
+    const uint64_t total = boff[nb];
+    uint64_t b[2];
+    for (int e = 0; e < 2; ++e) {
+        const uint64_t q = (uint64_t)k + (uint64_t)e;  // cut number 0..S
+        if (q == 0) { b[e] = 0; continue; }
+        if (q >= S) { b[e] = nb; continue; }
+        // first batch whose candidate prefix reaches ceil(total q / S), without overflow
+        const uint64_t t = (total / S) * q + ((total % S) * q + S - 1) / S;
+        uint64_t lo = 0, hi = nb;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (boff[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        b[e] = lo;
+    }
+    out[0] = b[0];
+    out[1] = b[1];
+    out[2] = uoff[b[0]];
+    out[3] = uoff[b[1]];
+    out[4] = boff[b[0]];
+    out[5] = boff[b[1]];
+}
+
+void shard_cut(const uint64_t *boff, const uint64_t *uoff, uint64_t nb, uint32_t S, uint32_t k, uint64_t *out,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_shard_cut, dim3(1), dim3(64), 0, st, boff, uoff, nb, S, k, out);
+}
+
 __global__ __launch_bounds__(256) void k_unit_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units,
                                                    uint32_t *unit_batch) {
     uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rhg.h")
 RHG_OK, RHG_EINVAL, RHG_ENOMEM, RHG_EDEVICE, RHG_ERANGE, RHG_ETRUNC, RHG_EBUSY = 0, -1, -2, -3, -4, -5, -6
 RHG_FP64, RHG_FP32_RECHECK = 0, 1
 RHG_OPT_FP32_EXHAUSTIVE = 1
+RHG_OPT_SHARD_COUNT = 2
+RHG_OPT_SHARD_INDEX = 3
 
 
 class RhgError(RuntimeError):

@@ -132,3 +132,50 @@ def test_fullsize(torch_ctx, orc, n, alpha, kbar):
     assert bool(torch.equal(out32[:2 * m64], out64[:2 * m64])), "FP32+recheck bytes differ from FP64"
     assert st32["candidates"] == st64["candidates"]
     print("rechecks", st32["rechecks"], "of", st32["candidates"], "candidates", flush=True)
+
+
+def _edge_checksum(out, m):
+    """Order-independent 64-bit checksum of m (lo, hi) pairs (sum of a multiplicative hash, wrapping)."""
+    import torch
+    tot = torch.zeros((), dtype=torch.int64, device=out.device)
+    chunk = 1 << 26
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        e = out[2 * a:2 * b].view(-1, 2).long()
+        h = (e[:, 0] * -7046029254386353131) ^ (e[:, 1] * -4417276706812531889)  # odd 64-bit constants
+        h = h ^ (h >> 29)
+        tot += h.sum()
+    return int(tot)
+
+
+def test_fullsize_shares_partition_the_graph():
+    """n = 10^7, alpha = 0.75, kbar = 100: the 8 one-GPU shares (whole table,
+    1/8 of the queries by candidates) hold m edges in total, the whole graph's
+    edge set by an order-independent checksum, and about 1/8 of the candidates each."""
+    import torch
+    rhg.load()
+    torch.cuda.set_device(0)
+    p = rhg.params(10_000_000, 0.75, kbar=100.0, seed=1)
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    try:
+        out, m, st, _ = _count_emit(c, p)
+        ref = _edge_checksum(out, m)
+        del out
+        S, m_sum, h_sum, cands = 8, 0, 0, []
+        for k in range(S):
+            rhg.rhg_ctx_set_option(c, rhg.RHG_OPT_SHARD_COUNT, S)
+            rhg.rhg_ctx_set_option(c, rhg.RHG_OPT_SHARD_INDEX, k)
+            o, mk, sk, _ = _count_emit(c, p)
+            e = o[:2 * mk].view(-1, 2)
+            assert mk == 0 or bool((e[:, 0] < e[:, 1]).all())
+            m_sum += mk
+            h_sum = (h_sum + _edge_checksum(o, mk)) & ((1 << 64) - 1)
+            cands.append(sk["candidates"])
+            print("share", k, "edges", mk, "candidates", sk["candidates"], flush=True)
+            del o, e
+    finally:
+        rhg.rhg_ctx_destroy(c)
+    assert m_sum == m
+    assert h_sum == ref & ((1 << 64) - 1)
+    assert sum(cands) == st["candidates"]
+    assert max(cands) <= 1.1 * st["candidates"] / S  # cut on the candidate prefix: balanced to within a batch
