@@ -79,6 +79,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
         L.orc_sort_edges.restype = None
         L.orc_sort_edges.argtypes = [vp, i64]
+        L.orc_move.restype = None
+        L.orc_move.argtypes = [u64, d, d, vp, vp, vp, vp]
         L.orc_free.restype = None
         L.orc_free.argtypes = [vp]
         _lib = L
@@ -265,3 +267,20 @@ def cosh_R(R: float) -> float:
     """K = cosh R, the threshold the distance test compares against (host libm)."""
     import math
     return math.cosh(R)
+
+
+# --------------------------------------------------------------------------
+# Dynamic model (Sec. III-C, Algorithm 2)
+# --------------------------------------------------------------------------
+def move(theta: np.ndarray, r: np.ndarray, tau_phi: np.ndarray, tau_r: np.ndarray, alpha: float,
+         R: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """One movement step: rotation by tau_phi and Algorithm 2's radial step
+    tau_r (in units of cosh(alpha r)), reflected at 0 and R.  Returns new
+    (theta, r, tau_r); the inputs are not modified."""
+    th = np.ascontiguousarray(theta, dtype=np.float64).copy()
+    rr = np.ascontiguousarray(r, dtype=np.float64).copy()
+    tp = np.ascontiguousarray(tau_phi, dtype=np.float64)
+    tr = np.ascontiguousarray(tau_r, dtype=np.float64).copy()
+    lib().orc_move(len(th), float(alpha), float(R), _ptr(th), _ptr(rr), _ptr(tp), _ptr(tr))
+    return th, rr, tr
+

@@ -34,6 +34,9 @@
  *   orc_window / orc_band_sweep          -- Algorithm 1's band query: slabs,
  *        angle sort per slab, getMinMaxPhi bound (Sec. III-B inequality chain),
  *        binary search of the window, outward-only scan.
+ *   orc_move                             -- one movement step of the dynamic
+ *        model (Sec. III-C: rotation, Algorithm 2's radial step, reflection
+ *        at 0 and R), in the reading under which Theorem 1 holds (below).
  *
  * Readings where the paper is silent or ambiguous (all listed in the design
  * notes of the repository): strict "< R"; half-open slabs with r = R in the
@@ -564,3 +567,50 @@ void orc_sort_edges(int32_t *pairs, int64_t m) {
     }
     free(k);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Dynamic model: one movement step (Sec. III-C, Algorithm 2, Theorem 1).     */
+/*                                                                            */
+/* Rotation: theta' = (theta + tau_phi) mod 2 pi, into [0, fl(2 pi)).         */
+/* Radial step: Algorithm 2 adds tau_r to a transform of r under which the    */
+/* radius density of Eq. 1 is uniform and maps back.  Under the density       */
+/* alpha sinh(alpha r) / (cosh(alpha R) - 1) that transform is                */
+/* w = cosh(alpha r), uniform on [1, cosh(alpha R)] (the interval starting at */
+/* 1 that the paper's figure of the movement shows); the printed sinh is not  */
+/* uniform near the centre and would not preserve the density, as Theorem 1   */
+/* states it does.  The step is taken in the equivalent variable               */
+/*   s = (w - 1) / 2 = sinh^2(alpha r / 2),  uniform on [0, S], S = sinh^2(alpha R / 2),   */
+/* by s + tau_r / 2, which keeps its precision near the centre.  A step that  */
+/* leaves [0, S] is reflected at the end it crosses (mirror), as often as it  */
+/* crosses one, and each reflection negates tau_r (the node bounces):         */
+/*   y = s + tau_r / 2,  k = floor(y / S);                                    */
+/*   s' = y - k S (k even) or (k + 1) S - y (k odd),  tau_r' = (-1)^k tau_r.  */
+/* Then r' = 2 asinh(sqrt(s')) / alpha, clamped to [0, R].  Reflection maps    */
+/* the uniform law on [0, S] to itself for each step size when both signs of  */
+/* the step are equally likely (Theorem 1 then holds exactly at every step).  */
+/* ------------------------------------------------------------------------- */
+void orc_move(uint64_t n, double alpha, double R, double *theta, double *r, const double *tau_phi,
+              double *tau_r) {
+    const double hS = sinh(alpha * R / 2.0);
+    const double S = hS * hS;
+    for (uint64_t i = 0; i < n; ++i) {
+        /* rotation */
+        double t = theta[i] + tau_phi[i];
+        t = t - ORC_TWO_PI * floor(t / ORC_TWO_PI);
+        if (t >= ORC_TWO_PI) t = 0.0;
+        if (t < 0.0) t = 0.0;
+        theta[i] = t;
+        /* radial step on s = sinh^2(alpha r / 2), reflected into [0, S] */
+        const double h = sinh(alpha * r[i] / 2.0);
+        const double y = h * h + tau_r[i] / 2.0;
+        const double k = floor(y / S);
+        const int odd = fmod(fabs(k), 2.0) == 1.0;
+        double s2 = odd ? (k + 1.0) * S - y : y - k * S;
+        if (s2 < 0.0) s2 = 0.0;
+        if (s2 > S) s2 = S;
+        if (odd) tau_r[i] = -tau_r[i];
+        double r2 = 2.0 * asinh(sqrt(s2)) / alpha;
+        r[i] = r2 > R ? R : r2;
+    }
+}
+
