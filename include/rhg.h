@@ -178,6 +178,25 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
                                    const double *table5xn, double R, rhg_precision precision, int on_device,
                                    rhg_graph **out);
 
+/* Dynamic model (Sec. III-C): one movement step of n nodes, in place, on
+ * the context stream (asynchronous; no host synchronisation).
+ *   theta[n], r[n]  device FP64 angles in [0, 2pi) and radii in [0, R]; updated.
+ *   tau_phi[n]      device FP64 angular steps (radians); read only.
+ *   tau_r[n]        device FP64 radial steps in units of cosh(alpha r) (the
+ *                   transform of Algorithm 2 under which Eq. 1's radius law is
+ *                   uniform); negated where the step is reflected an odd
+ *                   number of times (the node bounces off the centre or rim).
+ * theta' = (theta + tau_phi) mod 2pi; cosh(alpha r') = cosh(alpha r) + tau_r,
+ * mirrored at 1 and cosh(alpha R) as often as it crosses them (computed on
+ * sinh^2(alpha r / 2), which keeps relative precision near the centre).  With
+ * both signs of each step size equally likely the point density is preserved
+ * exactly (Theorem 1).  The arrays are owned by the caller and must not
+ * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
+ * finite and positive.  Regenerate the graph of the moved points with
+ * rhg_generate_from_coords (coords_on_device = 1). */
+rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,
+                    const double *tau_phi, double *tau_r);
+
 /* Two-phase form for caller-owned output (e.g. a PyTorch tensor):
  * rhg_count plans and counts (m), rhg_emit writes the m pairs into
  * dev_pairs (device, >= 2*m int32, capacity_pairs in pairs; RHG_ETRUNC if

@@ -53,6 +53,9 @@ void units_per_batch(const uint64_t *batch_cand, uint64_t nb, uint64_t *nunits, 
 // units per batch (nunits: nb scratch, used above one workgroup's size).
 void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nunits, uint64_t *uoff, void *scratch,
                 hipStream_t st);
+// Dynamic model: one movement step of n nodes in place (S = sinh^2(alpha R / 2)).
+void move(uint64_t n, double alpha, double R, double S, double *theta, double *r, const double *tau_phi,
+          double *tau_r, hipStream_t st);
 // Query share k of S: out = {b0, b1, u0, u1, c0, c1}, the batch range [b0, b1)
 // cut where the candidate prefix boff crosses k/S and (k+1)/S of the total,
 // its unit range (uoff) and candidate range (boff).  One thread.

@@ -704,6 +704,22 @@ extern "C" rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const do
     return s;
 }
 
+extern "C" rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,
+                               const double *tau_phi, double *tau_r) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return RHG_EINVAL;
+    if (!(std::isfinite(alpha) && alpha > 0.0 && std::isfinite(R) && R > 0.0)) return RHG_EINVAL;
+    if (n == 0) return RHG_OK;
+    if (!theta || !r || !tau_phi || !tau_r) return RHG_EINVAL;
+    const double h = std::sinh(alpha * R / 2.0);
+    const double S = h * h;  // sinh^2(alpha R / 2): the top of the uniform radius coordinate
+    if (!(std::isfinite(S) && S > 0.0)) return RHG_EINVAL;
+    RHG_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();
+    rhgk::move(n, alpha, R, S, theta, r, tau_phi, tau_r, c->stream);
+    return hip_status(hipGetLastError());
+}
+
 extern "C" rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_graph **plan, uint64_t *m) {
     if (!plan || !m) return RHG_EINVAL;
     Request rq;

@@ -96,6 +96,7 @@ def load(path: Optional[str] = None):
         "rhg_generate": (i32, [vp, P(rhg_params), P(vp)]),
         "rhg_generate_from_coords": (i32, [vp, u64, vp, vp, d, i32, i32, P(vp)]),
         "rhg_generate_from_table": (i32, [vp, u64, vp, vp, vp, d, i32, i32, P(vp)]),
+        "rhg_move": (i32, [vp, u64, d, d, vp, vp, vp, vp]),
         "rhg_count": (i32, [vp, P(rhg_params), P(vp), P(u64)]),
         "rhg_emit": (i32, [vp, vp, vp, u64]),
         "rhg_graph_num_edges": (i32, [vp, P(u64)]),
@@ -226,6 +227,18 @@ def rhg_generate_from_table(ctx, theta, r, table5xn, R: float, precision: int = 
     _check(load().rhg_generate_from_table(ctx, n, _ptr(theta), _ptr(r), _ptr(table5xn), float(R), int(precision),
                                           on_dev, ctypes.byref(g)), "rhg_generate_from_table")
     return g
+
+
+def rhg_move(ctx, theta, r, tau_phi, tau_r, alpha: float, R: float):
+    """One movement step in place.  theta, r, tau_phi, tau_r: float64 torch
+    tensors on the GPU of equal length (or device addresses with n given by
+    theta's length); theta, r and tau_r are updated on the context stream."""
+    n = int(theta.numel()) if hasattr(theta, "numel") else len(theta)
+    for x in (r, tau_phi, tau_r):
+        if hasattr(x, "numel") and int(x.numel()) != n:
+            raise ValueError("rhg_move: arrays of different lengths")
+    _check(load().rhg_move(ctx, n, float(alpha), float(R), _ptr(theta), _ptr(r), _ptr(tau_phi), _ptr(tau_r)),
+           "rhg_move")
 
 
 def rhg_count(ctx, p: rhg_params) -> Tuple[ctypes.c_void_p, int]:
