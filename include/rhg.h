@@ -190,7 +190,9 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
  * mirrored at 1 and cosh(alpha R) as often as it crosses them (computed on
  * sinh^2(alpha r / 2), which keeps relative precision near the centre).  With
  * both signs of each step size equally likely the point density is preserved
- * exactly (Theorem 1).  The arrays are owned by the caller and must not
+ * exactly (Theorem 1).  A zero step leaves the coordinate bit for bit as it
+ * is, so nodes with tau_phi = tau_r = 0 stay put (rhg_update relies on it).
+ * The arrays are owned by the caller and must not
  * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
  * finite and positive.  Regenerate the graph of the moved points with
  * rhg_generate_from_coords (coords_on_device = 1). */

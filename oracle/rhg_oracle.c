@@ -600,7 +600,9 @@ void orc_move(uint64_t n, double alpha, double R, double *theta, double *r, cons
         if (t >= ORC_TWO_PI) t = 0.0;
         if (t < 0.0) t = 0.0;
         theta[i] = t;
-        /* radial step on s = sinh^2(alpha r / 2), reflected into [0, S] */
+        /* radial step on s = sinh^2(alpha r / 2), reflected into [0, S]; a zero
+         * step leaves the radius exactly as it is */
+        if (tau_r[i] == 0.0) continue;
         const double h = sinh(alpha * r[i] / 2.0);
         const double y = h * h + tau_r[i] / 2.0;
         const double k = floor(y / S);

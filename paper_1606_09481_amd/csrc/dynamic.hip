@@ -26,6 +26,7 @@ __global__ __launch_bounds__(256) void k_move(uint64_t n, double alpha, double R
     // radial step: y = s + tau_r / 2 folded into [0, S]; k = floor(y / S)
     // boundary crossings, each a mirror reflection that negates the step
     const double tr = tau_r[i];
+    if (tr == 0.0) return;  // a zero step leaves the radius exactly as it is
     const double h = sinh(alpha * r[i] / 2.0);
     const double y = h * h + tr / 2.0;
     const double k = floor(y / S);
