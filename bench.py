@@ -11,9 +11,12 @@ reported beside it (its edge list is checked byte-identical).
 
 Also reported: per-phase device times (HIP events on the library stream),
 the roofline of the dominant kernel, the CPU oracle on a bounded sample of
-the same workload (cpu_baseline), and the request server on a stream of
+the same workload (cpu_baseline), the request server on a stream of
 2000 mixed requests (serving): closed-loop saturation throughput X, then
-Poisson arrivals at 0.7 X with p50/p99 latency and aggregate edges/s.
+Poisson arrivals at 0.7 X with p50/p99 latency and aggregate edges/s; one
+GPU's share of an 8-GPU run (share: whole table, 1/8 of the queries); and
+the dynamic model's movement step with the regeneration of the moved graph
+(dynamic).
 """
 from __future__ import annotations
 
@@ -96,6 +99,7 @@ def run_gpu(args):
         }
     rhg.rhg_ctx_destroy(ctx)
     del out, ref_edges
+    torch.cuda.empty_cache()
     return res
 
 
@@ -142,9 +146,66 @@ def run_shares(args):
     finally:
         rhg.rhg_ctx_destroy(ctx)
         del out
+        torch.cuda.empty_cache()
     return {"count": S, "what": "whole table sampled, sorted and planned; count and emit for 1/%d of the "
                                 "queries (by candidates)" % S,
             "max_ms": max(x["ms"] for x in per), "mean_ms": sum(x["ms"] for x in per) / S, "shares": per}
+
+
+def run_dynamic(args):
+    """Dynamic model (Sec. III-C) at the benchmark size: one movement step of
+    all nodes and of 12% of them (tau_phi in (-1, 1), tau_r in (-10, 1), the
+    paper's ranges), timed with HIP events on the context stream, then the
+    graph of the moved points regenerated from the device arrays."""
+    import torch
+    from paper_1606_09481_amd import rhg
+
+    rhg.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = rhg.rhg_ctx_create(0, stream)
+    n, alpha = args.n, args.alpha
+    R = rhg.rhg_target_radius(n, alpha, args.kbar)
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    u = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+    th = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * (2 * math.pi)
+    r = (2.0 * torch.asinh(torch.sqrt(u) * math.sinh(alpha * R / 2.0)) / alpha).clamp_(max=R)  # Eq. 1
+    res = {"n": n, "R": R, "bytes_per_node": 48}
+    try:
+        for frac in (1.0, 0.12):
+            sel = torch.rand(n, device="cuda", generator=g) < frac
+            tp = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 2 - 1, 0.0)
+            tr = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 11 - 10, 0.0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            times = []
+            for it in range(2 + 10):
+                ev[0].record(stream)
+                rhg.rhg_move(ctx, th, r, tp, tr, alpha, R)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                if it >= 2:
+                    times.append(ev[0].elapsed_time(ev[1]))
+            t = sum(times) / len(times)
+            gbs = 48.0 * n / (t * 1e-3) / 1e9  # read theta, r, tau_phi, tau_r; write theta, r
+            res["move_all" if frac == 1.0 else "move_12pct"] = {"ms": t, "GB_s": gbs, "frac_of_hbm_peak": gbs / 8000.0}
+        gen = []
+        for it in range(1 + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gr = rhg.rhg_generate_from_coords(ctx, th, r, R)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            m = rhg.rhg_graph_num_edges(gr)
+            rhg.rhg_graph_free(gr)
+            if it >= 1:
+                gen.append(t1 - t0)
+        res["regenerate"] = {"ms": 1e3 * sum(gen) / len(gen), "edges": m,
+                             "what": "rhg_generate_from_coords on the moved device arrays (library-owned output)"}
+    finally:
+        rhg.rhg_ctx_destroy(ctx)
+        del th, r, u
+        torch.cuda.empty_cache()
+    return res
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_traffic_n1e7_a075_k100.md")
@@ -321,6 +382,7 @@ def main():
                          "scales HBM byte counters under rocprofv3 --pmc)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-model timing")
     ap.add_argument("--shares", type=int, default=8,
                     help="also time each of this many one-GPU query shares (0: skip)")
     args = ap.parse_args()
@@ -363,10 +425,12 @@ def main():
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
         "roofline": roof,
     }
-    if args.shares > 1:
-        line["share"] = run_shares(args)
     if not args.no_serve:
         line["serving"] = run_serving(args)
+    if args.shares > 1:
+        line["share"] = run_shares(args)
+    if not args.no_dynamic:
+        line["dynamic"] = run_dynamic(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args, f64["m"])
     print(json.dumps(line), flush=True)

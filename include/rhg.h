@@ -111,8 +111,10 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run
- * on (e.g. the caller's PyTorch stream), or NULL for a library-owned stream.
- * The context keeps device work buffers between calls (grown as needed). */
+ * on (e.g. the caller's PyTorch stream), or NULL for a library-owned blocking
+ * stream, which is ordered with work on the device's null stream (PyTorch's
+ * default stream has handle 0 and lands here).  The context keeps device work
+ * buffers between calls (grown as needed). */
 rhg_status rhg_ctx_create(int device, void *hip_stream, rhg_ctx **out);
 
 /* Route the context's device allocations through the caller (e.g. a caching
@@ -191,7 +193,7 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
  * sinh^2(alpha r / 2), which keeps relative precision near the centre).  With
  * both signs of each step size equally likely the point density is preserved
  * exactly (Theorem 1).  A zero step leaves the coordinate bit for bit as it
- * is, so nodes with tau_phi = tau_r = 0 stay put (rhg_update relies on it).
+ * is, so nodes with tau_phi = tau_r = 0 stay put.
  * The arrays are owned by the caller and must not
  * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
  * finite and positive.  Regenerate the graph of the moved points with

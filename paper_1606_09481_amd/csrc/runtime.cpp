@@ -174,7 +174,9 @@ extern "C" rhg_status rhg_ctx_create(int device, void *hip_stream, rhg_ctx **out
         c->stream = (hipStream_t)hip_stream;
         c->own_stream = false;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        // a blocking stream: ordered with work on the device's null stream (e.g.
+        // PyTorch's default stream), so caller arrays written there are ready
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess) {
             delete c;
             return RHG_EDEVICE;
         }
