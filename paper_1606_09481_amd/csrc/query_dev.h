@@ -45,25 +45,17 @@ __device__ __forceinline__ int half_width(const Geo &g, const QPlan &q, int j, d
     return 0;
 }
 
-// First position of slab j with quantised angle >= x / > x: a direct-mapped
-// bucket lookup, then a binary search inside the bucket.
-__device__ __forceinline__ uint32_t lower_pos(const Geo &g, int j, uint32_t x) {
+// First position of slab j with quantised angle >= t, for t <= 2^QBITS (t =
+// 2^QBITS falls in the last bucket and gives the slab end).
+__device__ __forceinline__ uint32_t first_at_least(const Geo &g, int j, uint32_t t) {
     const uint32_t *T = g.btab + g.bto[j];
-    uint32_t b = x >> g.bshift[j];
+    const int sh = g.bshift[j];
+    const uint32_t bmax = QMASK >> sh;
+    const uint32_t b = min(t >> sh, bmax);
     uint32_t lo = T[b], hi = T[b + 1];
     while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((g.keys[mid] & QMASK) < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-__device__ __forceinline__ uint32_t upper_pos(const Geo &g, int j, uint32_t x) {
-    const uint32_t *T = g.btab + g.bto[j];
-    uint32_t b = x >> g.bshift[j];
-    uint32_t lo = T[b], hi = T[b + 1];
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((g.keys[mid] & QMASK) <= x) lo = mid + 1; else hi = mid;
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((g.keys[mid] & QMASK) < t) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
@@ -94,36 +86,23 @@ __device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j,
     double delta = 0.0;
     const int whole = (j == 0) ? 1 : half_width(g, qp, j, &delta);
     if (j == i) {
-        uint32_t cnt;
-        if (whole) {
-            if (qv < QHALF) {
-                cnt = upper_pos(g, j, qv + QHALF) - s - 1;
-            } else {
-                cnt = (be - s - 1) + (lower_pos(g, j, qv - QHALF) - bs);
-            }
-        } else {
-            double hi = thv + delta;
-            if (hi < TWO_PI) {
-                cnt = upper_pos(g, j, qang(hi)) - s - 1;
-            } else {
-                cnt = (be - s - 1) + (upper_pos(g, j, qang(hi - TWO_PI)) - bs);
-            }
-        }
-        return make_uint2(s + 1, cnt);
+        // forward range from s + 1 to the first position with key >= t (a key
+        // "> x" is one ">= x + 1"), past the slab end when it wraps; one
+        // search for all four cases (whole slab or not, wrapping or not)
+        const double hi = thv + delta;
+        const bool wrap = whole ? qv >= QHALF : hi >= TWO_PI;
+        const uint32_t t = whole ? (wrap ? qv - QHALF : qv + QHALF + 1u) : qang(wrap ? hi - TWO_PI : hi) + 1u;
+        const uint32_t P = first_at_least(g, j, t);
+        return make_uint2(s + 1, wrap ? (be - s - 1) + (P - bs) : P - s - 1);
     }
     if (whole) return make_uint2(bs, nj);
-    double lo = thv - delta, hi = thv + delta;
-    uint2 r;
-    if (lo < 0.0) {
-        r = range_pos(g, j, qang(lo + TWO_PI), qang(hi));
-        return make_uint2(r.x, (be - r.x) + (r.y - bs));
-    }
-    if (hi >= TWO_PI) {
-        r = range_pos(g, j, qang(lo), qang(hi - TWO_PI));
-        return make_uint2(r.x, (be - r.x) + (r.y - bs));
-    }
-    r = range_pos(g, j, qang(lo), qang(hi));
-    return make_uint2(r.x, r.y - r.x);
+    // [lo, hi] wraps past 0 or past 2 pi (not both: the half-width is below
+    // pi / 2); one search of both ends either way, so that lanes of one
+    // wavefront on different sides of the wrap take the same path
+    const double lo = thv - delta, hi = thv + delta;
+    const bool wlo = lo < 0.0, whi = hi >= TWO_PI;
+    const uint2 r = range_pos(g, j, qang(wlo ? lo + TWO_PI : lo), qang(whi ? hi - TWO_PI : hi));
+    return (wlo || whi) ? make_uint2(r.x, (be - r.x) + (r.y - bs)) : make_uint2(r.x, r.y - r.x);
 }
 
 // Windows are stored slab-major: window (v, j) of sorted query v (slab(v) <= j)

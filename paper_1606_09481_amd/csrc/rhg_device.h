@@ -74,9 +74,9 @@ struct Geo {
 };
 
 __device__ __forceinline__ uint32_t qang(double x) {
-    double y = x * QSCALE;
-    if (!(y > 0.0)) return 0u;
-    if (y >= 134217727.0) return QMASK;
+    // min(floor(x 2^27 / fl(2 pi)), 2^27 - 1), 0 below 0 (and for NaN); clamped
+    // as doubles so that it compiles without branches
+    const double y = fmin(fmax(x * QSCALE, 0.0), 134217727.0);
     return (uint32_t)y;
 }
 
