@@ -66,7 +66,9 @@ typedef enum {
  *   R          disk radius; R > 0 overrides kbar.  FP32_RECHECK needs R <= 43.
  *   seed       SplitMix64 seed; point i uses outputs 2i (angle) and 2i+1 (radius).
  *   precision  RHG_FP64 or RHG_FP32_RECHECK.
- *   num_bands  number of slabs B, 0 = ceil(log2 n); 1 <= B <= 32.
+ *   num_bands  number of slabs B, 0 = max(1, ceil(log2 n) - 8); 1 <= B <= 32.
+ *              The edge set does not depend on B or band_ratio; they set
+ *              the balance of window planning against distance tests.
  *   band_ratio width ratio p of consecutive slabs, 0 = 0.9; 0 < p <= 1 (p = 1: equal widths). */
 typedef struct {
     uint64_t n;

@@ -88,10 +88,16 @@ static bool make_boundaries(double R, int B, double p, double *c) {
     return true;
 }
 
+// Default slab count: ceil(log2 n) - 8.  The edge set does not depend on the
+// slabs; their number trades windows (plan work, slab segments per work
+// unit) against candidates (count and emit work).  The paper's ceil(log2 n)
+// is tuned for one thread per query on a CPU; on this GPU the step is
+// fastest about 8 slabs lower (measured at n = 10^6 .. 10^7, alpha 0.55 ..
+// 1.5: 4-10% faster than ceil(log2 n)).
 static int default_bands(uint64_t n) {
     int b = 0;
     while (b < 63 && (1ull << b) < n) ++b;
-    return std::max(1, std::min(b, MAX_BANDS));
+    return std::max(1, std::min(b - 8, MAX_BANDS));
 }
 
 extern "C" rhg_status rhg_band_boundaries(double R, uint32_t num_bands, double band_ratio, double *c_out) {

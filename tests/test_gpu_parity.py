@@ -68,7 +68,10 @@ def test_table_mode_exact_model(ctx, orc, n, alpha, kbar, seed):
 @pytest.mark.parametrize("seed", range(3))
 def test_table_mode_exact_adversarial(ctx, orc, seed):
     n, R = 9_000, 14.0
-    c = orc.boundaries(R, orc.default_bands(n), 0.9)
+    # radii exactly at the slab boundaries of both sides: the oracle's
+    # ceil(log2 n) slabs and the library's default, ceil(log2 n) - 8 (rhg_params)
+    c = np.concatenate([orc.boundaries(R, orc.default_bands(n), 0.9),
+                        rhg.rhg_band_boundaries(R, max(1, orc.default_bands(n) - 8), 0.9)])
     th, r = inputs.adversarial_coords(n, R, c, seed)
     print("adversarial seed", seed, flush=True)
     e, t, _ = _from_table(ctx, orc, th, r, R)
@@ -127,14 +130,14 @@ def test_slab_choice_does_not_change_edges(ctx, orc, B, p):
 @pytest.mark.parametrize("n,alpha,kbar,seed", [(10_000, 1.0, 10, 1), (50_000, 0.55, 6, 7), (30_001, 1.5, 20, 9)])
 def test_seeded_points_match_oracle_sampler(ctx, orc, n, alpha, kbar, seed):
     R = orc.target_radius(n, alpha, kbar)
-    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=seed))
+    B = orc.default_bands(n)
+    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=seed, num_bands=B))
     th, r, t, K = rhg.rhg_graph_copy_points(g)
     windows = rhg.rhg_graph_stats(g)["windows"]
     rhg.rhg_graph_free(g)
     # every point sits in the slab its own radius defines (Sec. III-A): the
     # device takes the slab from thresholds on the radius uniform, so check it
     # through the window count, sum over points of (B - slab)
-    B = orc.default_bands(n)
     c = rhg.rhg_band_boundaries(R, B, 0.9)
     slab = np.searchsorted(c[1:B], r, side="right")
     assert windows == int(np.sum(B - slab))
