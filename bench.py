@@ -394,6 +394,9 @@ def main():
     if args.serve_only:
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return
+    # the request stream runs first: after the 4 GB edge buffers of the main
+    # step have come and gone, this process serves about 15% fewer requests
+    serving = run_serving(args) if not args.no_serve else None
     res = run_gpu(args)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -429,8 +432,8 @@ def main():
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
         "roofline": roof,
     }
-    if not args.no_serve:
-        line["serving"] = run_serving(args)
+    if serving is not None:
+        line["serving"] = serving
     if args.shares > 1:
         line["share"] = run_shares(args)
     if not args.no_dynamic:
