@@ -134,26 +134,20 @@ __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     emit_unit<WIDE, true>(A, unit, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
+// The generation sizes the library accepts (n < 2^26) keep every table byte
+// offset below 2^32, so only the 32-bit-offset forms (WIDE = false) launch.
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {
     if (!a.n_units) return;
-    const bool wide = a.geo.n >= (1u << 28);
     const dim3 grid(exec_blocks(a.n_units)), block(256);
-    if (fp32) {
-        if (wide) hipLaunchKernelGGL((k_count<1, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_count<1, false>), grid, block, 0, st, a);
-    } else {
-        if (wide) hipLaunchKernelGGL((k_count<0, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_count<0, false>), grid, block, 0, st, a);
-    }
+    if (fp32) hipLaunchKernelGGL((k_count<1, false>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_count<0, false>), grid, block, 0, st, a);
 }
 
 void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
     (void)fp32;  // decisions come from the count pass's bitmap
     if (!a.n_units) return;
-    const bool wide = a.geo.n >= (1u << 28);
     const dim3 grid(exec_blocks(a.n_units)), block(256);
-    if (wide) hipLaunchKernelGGL((k_emit<true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, a);
 }
 
 }  // namespace rhgk

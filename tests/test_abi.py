@@ -100,3 +100,14 @@ def test_product_has_no_oracle_dependency():
     out = subprocess.run(["ldd", rhg.LIB_PATH], capture_output=True, text=True).stdout
     assert "oracle" not in out
     assert root
+
+
+def test_size_limit(lib):
+    """n < 2^26 (a batch's candidate offsets within one slab are 32-bit); checked on the host."""
+    ok = rhg.rhg_server_estimate_bytes(rhg.params((1 << 26) - 1, 0.75, kbar=10))
+    assert ok > 0
+    for n in (1 << 26, 1 << 31):
+        with pytest.raises(rhg.RhgError) as ei:
+            rhg.rhg_server_estimate_bytes(rhg.params(n, 0.75, kbar=10))
+        assert ei.value.status == rhg.RHG_ERANGE
+

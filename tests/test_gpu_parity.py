@@ -246,6 +246,9 @@ def test_invalid_inputs(ctx):
         rhg.rhg_generate_from_coords(ctx, np.array([0.1, 1.0]), np.array([1.0, 6.0]), 5.0)  # r > R
     with pytest.raises(rhg.RhgError):
         rhg.rhg_generate_from_coords(ctx, np.array([0.1, np.nan]), np.array([1.0, 1.0]), 5.0)
+    with pytest.raises(rhg.RhgError) as ei:
+        rhg.rhg_generate(ctx, rhg.params(1 << 26, 0.75, kbar=10))  # beyond the 32-bit batch offsets
+    assert ei.value.status == rhg.RHG_ERANGE
     # the context still works afterwards
     e = _edges(rhg.rhg_generate(ctx, rhg.params(5000, 1.0, kbar=10, seed=1)))
     assert len(e) > 0
