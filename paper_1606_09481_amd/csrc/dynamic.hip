@@ -18,10 +18,13 @@ __global__ __launch_bounds__(256) void k_move(uint64_t n, double alpha, double R
                                               const double *tau_phi, double *tau_r) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // rotation, into [0, fl(2 pi))
+    // rotation, into [0, fl(2 pi)); inside it the quotient's floor is 0 (the
+    // rounded quotient of t < fl(2 pi) stays below 1), so the division is skipped
     double t = theta[i] + tau_phi[i];
-    t = t - TWO_PI * floor(t / TWO_PI);
-    if (t >= TWO_PI || t < 0.0) t = 0.0;
+    if (!(t >= 0.0 && t < TWO_PI)) {
+        t = t - TWO_PI * floor(t / TWO_PI);
+        if (t >= TWO_PI || t < 0.0) t = 0.0;
+    }
     theta[i] = t;
     // radial step: y = s + tau_r / 2 folded into [0, S]; k = floor(y / S)
     // boundary crossings, each a mirror reflection that negates the step
@@ -29,8 +32,11 @@ __global__ __launch_bounds__(256) void k_move(uint64_t n, double alpha, double R
     if (tr == 0.0) return;  // a zero step leaves the radius exactly as it is
     const double h = sinh(alpha * r[i] / 2.0);
     const double y = h * h + tr / 2.0;
-    const double k = floor(y / S);
-    const bool odd = fmod(fabs(k), 2.0) == 1.0;
+    double k = 0.0;  // y in [0, S): no crossing (floor of the quotient is 0, as above)
+    if (!(y >= 0.0 && y < S)) k = floor(y / S);
+    // parity of the integer k: |k| >= 2^53 is even (as fmod(|k|, 2) says)
+    const double ak = fabs(k);
+    const bool odd = ak < 9007199254740992.0 && (((unsigned long long)ak) & 1ull) != 0ull;
     double s2 = odd ? (k + 1.0) * S - y : y - k * S;
     if (s2 < 0.0) s2 = 0.0;
     if (s2 > S) s2 = S;
