@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) {
         const uint64_t unit = unit0 + q < A.n_units ? unit0 + q : A.n_units - 1;
-        u[q] = unit_setup(A, A.unit_base + unit, lane);
+        u[q] = unit_setup_chain(A, A.unit_base + unit, lane);
     }
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) slab_windows(g, A, u[q], u[q].jstart, st[q], cnt[q], excl[q], tot[q]);
@@ -104,6 +104,16 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
         if (lane == 0 && unit0 + q < A.n_units) {
             key[unit0 + q] = kq;
             id[unit0 + q] = (uint32_t)(A.unit_base + unit0 + q);
+            if (A.udesc) {
+                UnitDesc d;
+                d.b = u[q].b;
+                d.jmin = (uint32_t)u[q].jmin;
+                d.segmask = u[q].segmask;
+                d.pad = 0;
+                d.r0 = u[q].r0;
+                d.r1 = u[q].r1;
+                A.udesc[unit0 + q] = d;
+            }
         }
     }
 }
@@ -147,7 +157,11 @@ void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
     (void)fp32;  // decisions come from the count pass's bitmap
     if (!a.n_units) return;
     const dim3 grid(exec_blocks(a.n_units)), block(256);
-    hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, a);
+    // emit walks from the unit chain, not the descriptors: measured 0.015 ms
+    // faster at n = 10^7 (its early loads overlap the bitmap and offset reads)
+    QueryArgs b = a;
+    b.udesc = nullptr;
+    hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, b);
 }
 
 }  // namespace rhgk

@@ -245,7 +245,7 @@ struct UnitSetup {
     uint64_t rlo, rhi;
 };
 
-__device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
+__device__ __forceinline__ UnitSetup unit_setup_chain(const QueryArgs &A, uint64_t unit, int lane) {
     const Geo &g = A.geo;
     UnitSetup u;
     // unit, batch and range are wave-uniform: scalar registers, so the walk
@@ -271,6 +271,33 @@ __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t uni
     u.pos = (u.jstart < g.B) ? row[u.jstart] : bc;
     u.jmin = jmin;
     u.segmask = (uint32_t)__ballot(k < g.B && u.rhi > u.rlo && u.rhi > u.r0 && u.rlo < u.r1);
+    return u;
+}
+
+// The same from the unit's descriptor: one scalar load, after which the
+// lane's loads (its query's key, the batch's segment offsets, the windows)
+// are all independent of each other, instead of a chain of dependent loads.
+__device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
+    if (!A.udesc) return unit_setup_chain(A, unit, lane);
+    const Geo &g = A.geo;
+    UnitSetup u;
+    unit = uniform_u64(unit);
+    const UnitDesc d = A.udesc[unit - A.unit_base];
+    u.b = d.b;
+    u.jmin = (int)d.jmin;
+    u.segmask = d.segmask;
+    u.r0 = d.r0;
+    u.r1 = d.r1;
+    u.v = u.b * BATCH + lane;
+    u.valid = u.v < g.n;
+    u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
+    // segment starts: rlo of lane k = row[jmin + k] (row[jmin] = 0)
+    const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
+    const int k = u.jmin + lane;
+    u.rlo = (k <= g.B) ? row[k] : 0ull;
+    u.rhi = 0;
+    u.jstart = u.jmin;
+    u.pos = 0;
     return u;
 }
 
@@ -304,10 +331,12 @@ __device__ __forceinline__ void prefetch_windows(const QueryArgs &A, const UnitS
         const bool any = mk != 0u;
         const int j = u.jmin + (any ? __builtin_ctz(mk) : 0);
         mk &= mk - 1u;
-        const bool take = any && u.valid && j >= u.iv;
-        const uint64_t at = take ? g.winbase[j] + u.v : 0ull;
+        // the address does not wait for the lane's slab: winbase[j] + v stays
+        // below winbase[B] (slab j's block plus the later ones hold >= n
+        // entries), and a window of a slab below the lane's is masked after
+        const uint64_t at = (any && u.valid) ? g.winbase[j] + u.v : 0ull;
         const uint2 y = A.win[at];
-        x[s] = take ? y : make_uint2(0u, 0u);
+        x[s] = (any && u.valid && j >= u.iv) ? y : make_uint2(0u, 0u);
     }
 #pragma unroll
     for (int s = 0; s < SEG_PRE; ++s) wpre[s][lane] = x[s];

@@ -17,7 +17,7 @@ enum Slot {
     S_TH, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
-    S_SHARD,
+    S_SHARD, S_UDESC,
     S_COUNT
 };
 

@@ -67,6 +67,14 @@ void unit_batch_fill(const uint64_t *unit_off, uint64_t nb, uint64_t n_units, ui
 // a5 / a7 / a8: the band query.  count: edges per unit into unit_edges,
 // stats[0] += rechecks, stats[1] += filter/FP64 disagreements (exhaustive).
 // emit: pairs at unit_off_edges[u].
+// Per-unit walk descriptor (written with the unit keys, read by the count
+// pass): the unit's batch, first slab of the batch, slab segments met, and
+// flattened candidate range [r0, r1) within the batch.
+struct UnitDesc {
+    uint32_t b, jmin, segmask, pad;
+    uint64_t r0, r1;
+};
+
 struct QueryArgs {
     rhgd::Geo geo;
     const uint2 *win;
@@ -77,6 +85,7 @@ struct QueryArgs {
     const uint32_t *unit_order;    // execution order of units (sector-sorted), or null
     uint64_t n_units;              // units executed: global ids unit_base .. unit_base + n_units - 1
     uint64_t unit_base;            // (a query share runs a contiguous range of the units)
+    UnitDesc *udesc;               // per unit from unit_base (with the unit order), or null
     uint32_t *unit_edges;          // count: edges per unit
     unsigned long long *bits;      // count -> emit: BITMAP_WORDS words of decisions per unit
     const uint64_t *unit_edge_off; // emit

@@ -503,7 +503,11 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     // sector order of the units (for L2 reuse across a large plan; below
     // UNIT_ORDER_MIN units the tables fit in cache and the launches cost more)
     qa.unit_order = nullptr;
+    qa.udesc = nullptr;
     if (U >= UNIT_ORDER_MIN) {
+        // the unit-key pass also leaves each unit's walk descriptor for the count pass
+        qa.udesc = (rhgk::UnitDesc *)c->buf(S_UDESC, sizeof(rhgk::UnitDesc) * U);
+        if (!qa.udesc) return RHG_ENOMEM;
         rhgk::unit_order(qa, ukey, uorder, ukey2, uorder2, usort, st);
         qa.unit_order = uorder;
     }

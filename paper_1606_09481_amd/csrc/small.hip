@@ -302,6 +302,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         sA.unit_order = nullptr;
         sA.n_units = U;
         sA.unit_base = 0;
+        sA.udesc = nullptr;
         sA.unit_edges = D.uedges;
         sA.bits = D.bits;
         sA.unit_edge_off = D.ueoff;
