@@ -199,7 +199,7 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
  * is, so nodes with tau_phi = tau_r = 0 stay put.
  * The arrays are owned by the caller and must not
  * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
- * finite and positive.  Regenerate the graph of the moved points with
+ * finite and positive; RHG_ERANGE: n >= 2^31.  Regenerate the graph of the moved points with
  * rhg_generate_from_coords (coords_on_device = 1). */
 rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,
                     const double *tau_phi, double *tau_r);

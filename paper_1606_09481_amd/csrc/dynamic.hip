@@ -8,7 +8,8 @@
 // keeps the density (Theorem 1).  The step tau_r is given in units of
 // cosh(alpha r), i.e. s moves by tau_r / 2; the sinh^2 form keeps full relative
 // precision near the centre, where cosh(alpha r) - 1 would cancel.
-// One thread per node; the arrays are read and written once (HBM-bound).
+// One thread per node; the arrays are read and written once.  The step is
+// bound by its FP64 sinh and asinh, not by the 48 bytes it moves per node.
 #include "rhg_kernels.h"
 
 namespace rhgk {

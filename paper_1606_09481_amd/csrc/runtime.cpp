@@ -729,6 +729,7 @@ extern "C" rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R,
     if (!(std::isfinite(alpha) && alpha > 0.0 && std::isfinite(R) && R > 0.0)) return RHG_EINVAL;
     if (n == 0) return RHG_OK;
     if (!theta || !r || !tau_phi || !tau_r) return RHG_EINVAL;
+    if (n >= (1ull << 31)) return RHG_ERANGE;  // one thread per node in one launch
     const double h = std::sinh(alpha * R / 2.0);
     const double S = h * h;  // sinh^2(alpha R / 2): the top of the uniform radius coordinate
     if (!(std::isfinite(S) && S > 0.0)) return RHG_EINVAL;

@@ -76,6 +76,7 @@ def test_null_handles_rejected(lib):
     assert lib.rhg_generate(None, ctypes.byref(p), ctypes.byref(g)) == rhg.RHG_EINVAL
     assert lib.rhg_emit(None, None, None, 0) == rhg.RHG_EINVAL
     assert lib.rhg_move(None, 10, 1.0, 5.0, None, None, None, None) == rhg.RHG_EINVAL
+    assert lib.rhg_move(None, 0, 1.0, 5.0, None, None, None, None) == rhg.RHG_EINVAL  # null context first
     assert lib.rhg_graph_stats(None, None) == rhg.RHG_EINVAL
     lib.rhg_graph_free(None)
     lib.rhg_ctx_destroy(None)
