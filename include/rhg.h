@@ -60,8 +60,7 @@ typedef enum {
 } rhg_precision;
 
 /* Generation parameters (Algorithm 1 input: n, average degree, alpha = (gamma-1)/2).
- *   n          number of points, 2 <= n < 2^26 (RHG_ERANGE above: a 64-query
- *              batch's candidate offsets within one slab are 32-bit).
+ *   n          number of points, 2 <= n < 2^31 (RHG_ERANGE above: int32 indices).
  *   alpha      dispersion, > 0; with kbar (R <= 0) it must be > 1/2.
  *   kbar       target average degree, used when R <= 0: R = getTargetRadius(n, alpha, kbar).
  *   R          disk radius; R > 0 overrides kbar.  FP32_RECHECK needs R <= 43.

@@ -79,7 +79,8 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
     const int lane = threadIdx.x & 63;
     const uint64_t unit0 = ((uint64_t)blockIdx.x * 4 + (uint64_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) * UKEY_UPW;
     UnitSetup u[UKEY_UPW];
-    uint32_t st[UKEY_UPW], cnt[UKEY_UPW], excl[UKEY_UPW], tot[UKEY_UPW], p[UKEY_UPW];
+    uint32_t st[UKEY_UPW], cnt[UKEY_UPW], p[UKEY_UPW];
+    uint64_t excl[UKEY_UPW], tot[UKEY_UPW];
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) {
         const uint64_t unit = unit0 + q < A.n_units ? unit0 + q : A.n_units - 1;
@@ -89,13 +90,13 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
     for (int q = 0; q < UKEY_UPW; ++q) slab_windows(g, A, u[q], u[q].jstart, st[q], cnt[q], excl[q], tot[q]);
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) {
-        const uint32_t off = (uint32_t)(u[q].r0 > u[q].pos ? u[q].r0 - u[q].pos : 0);
+        const uint64_t off = u[q].r0 > u[q].pos ? u[q].r0 - u[q].pos : 0ull;
         const bool here = cnt[q] != 0u && excl[q] <= off && off - excl[q] < cnt[q];
         const uint64_t m = __ballot(here);
         const int l = m ? __ffsll((long long)m) - 1 : 0;
         const uint32_t be = g.bs[u[q].jstart + 1], nj = be - g.bs[u[q].jstart];
         uint32_t pp = g.bs[u[q].jstart];
-        if (lane == l && m) pp = position_of(make_uint2(st[q], excl[q]), off, be, nj);
+        if (lane == l && m) pp = position_of(make_uint2(st[q], 0u), (uint32_t)(off - excl[q]), be, nj);
         p[q] = wave_bcast_u32(pp, l);
     }
 #pragma unroll
@@ -144,13 +145,18 @@ __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     emit_unit<WIDE, true>(A, unit, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
-// The generation sizes the library accepts (n < 2^26) keep every table byte
-// offset below 2^32, so only the 32-bit-offset forms (WIDE = false) launch.
+// Below n = 2^28 every table byte offset fits 32 bits (WIDE = false).
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {
     if (!a.n_units) return;
+    const bool wide = a.geo.n >= (1u << 28);
     const dim3 grid(exec_blocks(a.n_units)), block(256);
-    if (fp32) hipLaunchKernelGGL((k_count<1, false>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_count<0, false>), grid, block, 0, st, a);
+    if (fp32) {
+        if (wide) hipLaunchKernelGGL((k_count<1, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_count<1, false>), grid, block, 0, st, a);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_count<0, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_count<0, false>), grid, block, 0, st, a);
+    }
 }
 
 void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
@@ -161,7 +167,8 @@ void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
     // faster at n = 10^7 (its early loads overlap the bitmap and offset reads)
     QueryArgs b = a;
     b.udesc = nullptr;
-    hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, b);
+    if (a.geo.n >= (1u << 28)) hipLaunchKernelGGL((k_emit<true>), grid, block, 0, st, b);
+    else hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, b);
 }
 
 }  // namespace rhgk

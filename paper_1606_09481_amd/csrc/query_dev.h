@@ -301,9 +301,24 @@ __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t uni
     return u;
 }
 
+// Exclusive wavefront scan of the 64 window counts of a slab segment, and
+// their total.  A window holds at most n points: while 64 n < 2^32 one 32-bit
+// scan is exact; beyond, the 16-bit halves are scanned apart (each sum < 2^22).
+__device__ __forceinline__ void window_scan(uint32_t cnt, uint32_t n, uint64_t &excl, uint64_t &tot) {
+    if (64ull * n < (1ull << 32)) {
+        const uint32_t incl = wave_incl_scan_u32(cnt);
+        tot = wave_bcast_u32(incl, 63);
+        excl = incl - cnt;
+    } else {
+        const uint32_t il = wave_incl_scan_u32(cnt & 0xffffu), ih = wave_incl_scan_u32(cnt >> 16);
+        tot = (uint64_t)wave_bcast_u32(il, 63) + ((uint64_t)wave_bcast_u32(ih, 63) << 16);
+        excl = (uint64_t)il + ((uint64_t)ih << 16) - cnt;
+    }
+}
+
 // Lane's window in slab j (0 count if none), scanned over the wavefront.
 __device__ __forceinline__ void slab_windows(const Geo &g, const QueryArgs &A, const UnitSetup &u, int j,
-                                             uint32_t &st, uint32_t &cnt, uint32_t &excl, uint32_t &tot) {
+                                             uint32_t &st, uint32_t &cnt, uint64_t &excl, uint64_t &tot) {
     st = 0;
     cnt = 0;
     if (u.valid && j >= u.iv) {
@@ -311,9 +326,7 @@ __device__ __forceinline__ void slab_windows(const Geo &g, const QueryArgs &A, c
         st = x.x;
         cnt = x.y;
     }
-    const uint32_t incl = wave_incl_scan_u32(cnt);
-    tot = wave_bcast_u32(incl, 63);
-    excl = incl - cnt;
+    window_scan(cnt, g.n, excl, tot);
 }
 
 // Windows of the first SEG_PRE segments of a unit, loaded together at the
@@ -342,10 +355,17 @@ __device__ __forceinline__ void prefetch_windows(const QueryArgs &A, const UnitS
     for (int s = 0; s < SEG_PRE; ++s) wpre[s][lane] = x[s];
 }
 
-// Lane's window in the seg-th segment of the unit (slab j) and its scan.
+// Lane's window in the seg-th segment of the unit (slab j, flattened start
+// pos within the batch), scanned and rebased to the unit: offsets below count
+// from the unit's first candidate in the segment, which keeps them in 32 bits
+// for any n (the unit spans at most UNIT candidates).  Returns the window's
+// count, pb with position = pb + offset (mod 2^32), its start relu (all ones:
+// before the unit; clamped to 2^30 far after it), and the segment's end e.
+constexpr uint32_t BEFORE_UNIT = 0xffffffffu;
+
 __device__ __forceinline__ void segment_windows(const QueryArgs &A, const UnitSetup &u, int seg, int j, int lane,
-                                                uint2 (*wpre)[64], uint32_t &st, uint32_t &cnt, uint32_t &excl,
-                                                uint32_t &tot) {
+                                                uint2 (*wpre)[64], uint64_t pos, uint32_t &cnt, uint32_t &pb,
+                                                uint32_t &relu, uint32_t &e) {
     const Geo &g = A.geo;
     uint2 x;
     if (seg < SEG_PRE) {
@@ -354,11 +374,15 @@ __device__ __forceinline__ void segment_windows(const QueryArgs &A, const UnitSe
         x = make_uint2(0u, 0u);
         if (u.valid && j >= u.iv) x = A.win[g.winbase[j] + u.v];
     }
-    st = x.x;
     cnt = x.y;
-    const uint32_t incl = wave_incl_scan_u32(cnt);
-    tot = wave_bcast_u32(incl, 63);
-    excl = incl - cnt;
+    uint64_t excl, tot;
+    window_scan(cnt, g.n, excl, tot);
+    const uint64_t a = (u.r0 > pos) ? u.r0 - pos : 0ull;
+    const uint64_t e64 = (u.r1 - pos < tot) ? u.r1 - pos : tot;
+    e = (uint32_t)(e64 > a ? e64 - a : 0ull);
+    const int64_t rel = (int64_t)(excl - a);
+    relu = rel < 0 ? BEFORE_UNIT : (rel > (1 << 30) ? (1u << 30) : (uint32_t)rel);
+    pb = x.x - (uint32_t)rel;
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -469,17 +493,15 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
         segs &= segs - 1u;
         const int j = u.jmin + bit;
         const uint64_t pos = lane_u64(u.rlo, bit);  // flattened offset of slab j's segment within the batch
-        uint32_t st, cnt, excl, tot;
+        uint32_t cnt, pb, relu, e;
         wave_lds_sync();
-        segment_windows(A, u, seg, j, lane, S.wpre, st, cnt, excl, tot);
-        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
-        const uint32_t e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
+        segment_windows(A, u, seg, j, lane, S.wpre, pos, cnt, pb, relu, e);
         const bool ne = cnt != 0u;
         const uint64_t nem = __ballot(ne);
         wave_lds_sync();
         if (ne) {
             const uint32_t rk = (uint32_t)__popcll(nem & lt);
-            S.pb[rk] = st - excl;
+            S.pb[rk] = pb;
             S.qd[0][rk] = mine.hep;
             S.qd[1][rk] = mine.hem;
             S.qd[2][rk] = mine.sh2;
@@ -491,11 +513,11 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
                 S.qf[2][rk] = mine.sh2_32;
             }
         }
-        uint32_t base = (uint32_t)__popcll(__ballot(ne && excl < a));
+        uint32_t base = (uint32_t)__popcll(__ballot(ne && relu == BEFORE_UNIT));
         const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
-        for (uint32_t t0 = a; t0 < e; t0 += 64u * VT) {
+        for (uint32_t t0 = 0; t0 < e; t0 += 64u * VT) {
             uint64_t M[VT];
-            step_starts<VT>(S.flag, lane, ne, excl, t0, M);
+            step_starts<VT>(S.flag, lane, ne, relu, t0, M);
             // Lanes past the segment's end take a dummy candidate (position bs,
             // rank masked into range) whose result is dropped.
             uint32_t p[VT], rk[VT];
@@ -589,7 +611,7 @@ struct EmitStep {
 struct EmitWalk {
     uint32_t segs;
     int seg;
-    uint32_t t0, e, base, word, be, nj, excl, out_rel;
+    uint32_t t0, e, base, word, be, nj, relu, out_rel;
     bool ne, in_seg;
 };
 
@@ -612,25 +634,23 @@ __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup
         w.segs &= w.segs - 1u;
         const int j = u.jmin + bit;
         const uint64_t pos = lane_u64(u.rlo, bit);
-        uint32_t st, cnt, tot;
+        uint32_t cnt, pb;
         wave_lds_sync();
-        segment_windows(A, u, w.seg, j, lane, S.wpre, st, cnt, w.excl, tot);
+        segment_windows(A, u, w.seg, j, lane, S.wpre, pos, cnt, pb, w.relu, w.e);
         ++w.seg;
-        const uint32_t a = (u.r0 > pos) ? (uint32_t)(u.r0 - pos) : 0u;
-        w.e = (u.r1 - pos < tot) ? (uint32_t)(u.r1 - pos) : tot;
         w.ne = cnt != 0u;
         const uint64_t nem = __ballot(w.ne);
         wave_lds_sync();
         if (w.ne) {
             const uint32_t rk = (uint32_t)__popcll(nem & lt);
-            S.pb[rk] = st - w.excl;
+            S.pb[rk] = pb;
             S.qi[rk] = myqi;
         }
-        w.base = (uint32_t)__popcll(__ballot(w.ne && w.excl < a));
+        w.base = (uint32_t)__popcll(__ballot(w.ne && w.relu == BEFORE_UNIT));
         w.be = g.bs[j + 1];
         w.nj = w.be - g.bs[j];
-        w.t0 = a;
-        w.in_seg = a < w.e;
+        w.t0 = 0;
+        w.in_seg = 0u < w.e;
     }
     // The step's VT decision words (uniform: scalar registers), read
     // unconditionally as one run (the bitmap carries VT words of padding past
@@ -648,7 +668,7 @@ __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup
         }
     }
     uint64_t M[VT];
-    step_starts<VT>(S.flag, lane, w.ne, w.excl, w.t0, M);
+    step_starts<VT>(S.flag, lane, w.ne, w.relu, w.t0, M);
     // ranks first, then every LDS read of the step, then positions and gathers:
     // no read sits behind a branch, so the reads of all sub-rounds share one wait
     uint32_t rk[VT], pb[VT];
@@ -712,7 +732,7 @@ __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int
     EmitWalk w;
     w.segs = u.segmask;
     w.seg = 0;
-    w.t0 = w.e = w.base = w.word = w.be = w.nj = w.excl = w.out_rel = 0u;
+    w.t0 = w.e = w.base = w.word = w.be = w.nj = w.relu = w.out_rel = 0u;
     w.ne = w.in_seg = false;
     EmitStep s0, s1;
     emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s0);

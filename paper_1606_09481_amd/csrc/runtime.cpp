@@ -273,11 +273,8 @@ int ceil_log2(uint64_t x) {
 }
 
 // Validates and fills the generation description.
-// n < 2^26: the count and emit walks hold a 64-query batch's flattened
-// candidate offsets within one slab segment (and the wavefront scan of its 64
-// window counts) in 32 bits, and a window holds at most the slab's points, so
-// 64 n < 2^32 bounds them.
-constexpr uint64_t N_MAX = 1ull << 26;
+// n < 2^31: positions and original indices are 32-bit (int32 output).
+constexpr uint64_t N_MAX = 1ull << 31;
 
 rhg_status describe(const Request &rq, Plan &pl) {
     if (rq.n < 2 || rq.n >= N_MAX) return rq.n < 2 ? RHG_EINVAL : RHG_ERANGE;

@@ -104,10 +104,10 @@ def test_product_has_no_oracle_dependency():
 
 
 def test_size_limit(lib):
-    """n < 2^26 (a batch's candidate offsets within one slab are 32-bit); checked on the host."""
-    ok = rhg.rhg_server_estimate_bytes(rhg.params((1 << 26) - 1, 0.75, kbar=10))
+    """n < 2^31 (int32 indices); checked on the host."""
+    ok = rhg.rhg_server_estimate_bytes(rhg.params((1 << 31) - 1, 0.75, kbar=10))
     assert ok > 0
-    for n in (1 << 26, 1 << 31):
+    for n in (1 << 31, 1 << 40):
         with pytest.raises(rhg.RhgError) as ei:
             rhg.rhg_server_estimate_bytes(rhg.params(n, 0.75, kbar=10))
         assert ei.value.status == rhg.RHG_ERANGE

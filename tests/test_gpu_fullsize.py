@@ -3,9 +3,10 @@ times (rhg_count + rhg_emit into one preallocated device buffer).
 
 Workloads: n = 10^7, alpha = 0.75, kbar = 100 (about 5.0e8 edges), the
 exponent sweep n = 4*10^6, kbar = 64, alpha in {0.55, 1.0, 1.5} (alpha = 0.55
-has hubs adjacent to about 10^6 points), and the largest accepted size,
-n = 2^26 - 1 at alpha = 0.55, kbar = 16 (hub batches whose windows in one slab
-add up to near 2^32 candidates), both precision forms.
+has hubs adjacent to about 10^6 points), and n = 2^26 - 1 at alpha = 0.55,
+kbar = 16 (hub batches whose windows in one slab add up to near 2^32
+candidates, the most a 32-bit scan holds), both precision forms.  Larger n:
+test_gpu_bign.py.
 
 The oracle cannot list 10^8..10^9 edges pair by pair, so it answers for
 sampled vertices: every neighbour of 96 random vertices, of the 16 innermost
@@ -29,7 +30,7 @@ from paper_1606_09481_amd import rhg
 pytestmark = pytest.mark.gpu
 
 CASES = [(10_000_000, 0.75, 100.0), (4_000_000, 0.55, 64.0), (4_000_000, 1.0, 64.0), (4_000_000, 1.5, 64.0),
-         ((1 << 26) - 1, 0.55, 16.0)]  # the largest n accepted, ragged, hubs near the 32-bit batch offsets
+         ((1 << 26) - 1, 0.55, 16.0)]  # hub batches just below 2^32 candidates per slab segment
 def _oracle_case(orc, n, alpha, kbar):
     R = orc.target_radius(n, alpha, kbar)
     th, r = orc.sample(n, alpha, R, 1)

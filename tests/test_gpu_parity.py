@@ -247,7 +247,7 @@ def test_invalid_inputs(ctx):
     with pytest.raises(rhg.RhgError):
         rhg.rhg_generate_from_coords(ctx, np.array([0.1, np.nan]), np.array([1.0, 1.0]), 5.0)
     with pytest.raises(rhg.RhgError) as ei:
-        rhg.rhg_generate(ctx, rhg.params(1 << 26, 0.75, kbar=10))  # beyond the 32-bit batch offsets
+        rhg.rhg_generate(ctx, rhg.params(1 << 31, 0.75, kbar=10))  # beyond int32 indices
     assert ei.value.status == rhg.RHG_ERANGE
     # the context still works afterwards
     e = _edges(rhg.rhg_generate(ctx, rhg.params(5000, 1.0, kbar=10, seed=1)))
