@@ -411,7 +411,9 @@ def main():
         traffic, traffic_src = measured_traffic(kkey) if bench_cfg else (None, None)
         return {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": kbytes, "avg_ms": kms,
-                "traffic_source": traffic_src}
+                "traffic_source": traffic_src,
+                # the measured bytes over the same time: the second fraction the workload's roofline asks for
+                "traffic_frac": (traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None}
 
     # the dominant kernel is the longer of the two query kernels of the timed FP64 step
     r_emit = roofline("k_emit<false>", "k_emit", emit_b, ph["emit"])
@@ -425,8 +427,12 @@ def main():
         "config": {"workload": "threshold RHG generation n=%d alpha=%g kbar=%g seed=%d (R=%.9f, %d edges)"
                                % (n, args.alpha, args.kbar, args.seed, f64["R"], f64["m"]),
                    "n": n, "alpha": args.alpha, "kbar": args.kbar, "R": f64["R"], "edges": f64["m"],
-                   "candidates": f64["candidates"], "windows": f64["windows"]},
+                   "candidates": f64["candidates"], "windows": f64["windows"],
+                   "candidates_per_edge": f64["candidates"] / max(1, f64["m"])},
         "phases_ms": ph,
+        # edges over the device time of slabs through emit only (Alg. 1 on a sampled, tabulated point set:
+        # the sample + key phase and the table phase excluded); `value` above is the whole generation
+        "edges_per_s_slabs_to_emit": f64["m"] / ((ph["device_total"] - ph["keys"] - ph["table_index"]) * 1e-3),
         "fp32_recheck": {"value": f32["edges_per_s"], "ms_per_step": 1e3 * f32["s_per_step"],
                          "rechecks": f32["rechecks"], "recheck_fraction": f32["rechecks"] / max(1, f32["candidates"]),
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
