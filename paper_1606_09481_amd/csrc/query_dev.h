@@ -332,7 +332,7 @@ __device__ __forceinline__ void slab_windows(const Geo &g, const QueryArgs &A, c
 // Windows of the first SEG_PRE segments of a unit, loaded together at the
 // unit's start (one memory round trip, before the pass issues any store) and
 // kept in LDS; later segments load their windows when reached.
-constexpr int SEG_PRE = 3;
+constexpr int SEG_PRE = 2;
 
 __device__ __forceinline__ void prefetch_windows(const QueryArgs &A, const UnitSetup &u, int lane,
                                                  uint2 (*wpre)[64]) {
@@ -408,9 +408,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int VT_COUNT = RHG_VT_COUNT;
 constexpr int VT_EMIT = RHG_VT_EMIT;
 
+// Also returns, per sub-round, the number of windows starting at or before
+// the lane's slot: the set bits of M below the lane (mbcnt) plus the lane's
+// own flag, i.e. popcount(M & bits 0..lane) in two instructions fewer.
 template <int VT>
 __device__ __forceinline__ void step_starts(uint8_t *flags, int lane, bool nonempty, uint32_t excl, uint32_t t0,
-                                            uint64_t (&M)[VT]) {
+                                            uint64_t (&M)[VT], uint32_t (&upto)[VT]) {
     if (nonempty && excl >= t0 && excl - t0 < 64u * VT) flags[excl - t0] = 1u;
     wave_lds_sync();
 #pragma unroll
@@ -418,6 +421,8 @@ __device__ __forceinline__ void step_starts(uint8_t *flags, int lane, bool nonem
         const uint32_t f = flags[i * 64 + lane];
         flags[i * 64 + lane] = 0u;
         M[i] = __ballot(f != 0u);
+        upto[i] = __builtin_amdgcn_mbcnt_hi((uint32_t)(M[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M[i], 0u)) +
+                  (f != 0u ? 1u : 0u);
     }
     wave_lds_sync();
 }
@@ -481,7 +486,6 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
     }
 #pragma unroll
     for (int i = 0; i < VT; ++i) S.flag[i * 64 + lane] = 0u;
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     prefetch_windows(A, u, lane, S.wpre);
@@ -517,7 +521,8 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
         const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
         for (uint32_t t0 = 0; t0 < e; t0 += 64u * VT) {
             uint64_t M[VT];
-            step_starts<VT>(S.flag, lane, ne, relu, t0, M);
+            uint32_t upto[VT];
+            step_starts<VT>(S.flag, lane, ne, relu, t0, M, upto);
             // Lanes past the segment's end take a dummy candidate (position bs,
             // rank masked into range) whose result is dropped.
             uint32_t p[VT], rk[VT];
@@ -526,7 +531,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
             for (int i = 0; i < VT; ++i) {
                 const uint32_t t = t0 + 64u * i + lane;
                 act[i] = t < e;
-                rk[i] = (base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
+                rk[i] = (base - 1u + upto[i]) & 63u;
                 base += (uint32_t)__popcll(M[i]);
                 const uint32_t pp = position_pb(S.pb[rk[i]], t, be, nj);
                 p[i] = act[i] ? pp : bs;
@@ -623,7 +628,7 @@ typedef const __attribute__((address_space(4))) unsigned long long *const_words_
 
 template <bool WIDE, bool SBITS>
 __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup &u, uint32_t myqi, uint32_t todo,
-                                             int lane, uint64_t le, uint64_t lt, EmitSmem &S, const_words_t cw,
+                                             int lane, uint64_t lt, EmitSmem &S, const_words_t cw,
                                              EmitWalk &w, EmitStep &s) {
     constexpr int VT = VT_EMIT;
     const Geo &g = A.geo;
@@ -668,13 +673,14 @@ __device__ __forceinline__ void emit_prepare(const QueryArgs &A, const UnitSetup
         }
     }
     uint64_t M[VT];
-    step_starts<VT>(S.flag, lane, w.ne, w.relu, w.t0, M);
+    uint32_t upto[VT];
+    step_starts<VT>(S.flag, lane, w.ne, w.relu, w.t0, M, upto);
     // ranks first, then every LDS read of the step, then positions and gathers:
     // no read sits behind a branch, so the reads of all sub-rounds share one wait
     uint32_t rk[VT], pb[VT];
 #pragma unroll
     for (int i = 0; i < VT; ++i) {
-        rk[i] = (w.base - 1u + (uint32_t)__popcll(M[i] & le)) & 63u;
+        rk[i] = (w.base - 1u + upto[i]) & 63u;
         w.base += (uint32_t)__popcll(M[i]);
     }
 #pragma unroll
@@ -720,7 +726,6 @@ __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int
         for (int k = lane; k < BITW + VT_EMIT; k += 64) S.bits[k] = k < BITW ? A.bits[unit * BITW + k] : 0ull;
 #pragma unroll
     for (int i = 0; i < VT_EMIT; ++i) S.flag[i * 64 + lane] = 0u;
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t at = uniform_u64(A.unit_edge_off[unit]);  // the resource must sit in scalar registers
     uint64_t cap = A.out_capacity > at ? A.out_capacity - at : 0ull;
@@ -735,12 +740,12 @@ __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int
     w.t0 = w.e = w.base = w.word = w.be = w.nj = w.relu = w.out_rel = 0u;
     w.ne = w.in_seg = false;
     EmitStep s0, s1;
-    emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s0);
+    emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, lt, S, cw, w, s0);
     while (s0.valid) {
-        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s1);  // gathers of the next step ...
+        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, lt, S, cw, w, s1);  // gathers of the next step ...
         emit_store(s0, out);                                            // ... in flight over these stores
         if (!s1.valid) break;
-        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, le, lt, S, cw, w, s0);
+        emit_prepare<WIDE, SBITS>(A, u, myqi, todo, lane, lt, S, cw, w, s0);
         emit_store(s1, out);
     }
 }
