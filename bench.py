@@ -357,11 +357,31 @@ def cpu_baseline(args, m_full):
     sweep = max((t3 - t2) - (t2 - t1), 1e-9)
     T_full = setup + sweep / frac
     m_est = len(e) / frac
+    # the same on one thread: sampling, table and slab sort of all points,
+    # band sweep over a tenth of the sample
+    f1 = frac / 10
+    q1s = int(args.n * f1)
+    t3b = time.perf_counter()
+    th1, r1 = oracle.sample(args.n, args.alpha, R, args.seed, threads=1)
+    tab1 = oracle.table(th1, r1, threads=1)
+    t4 = time.perf_counter()
+    oracle.band_sweep(th1, r1, tab1, R, math.cosh(R), threads=1, q0=0, q1=0)
+    t5 = time.perf_counter()
+    e1 = oracle.band_sweep(th1, r1, tab1, R, math.cosh(R), threads=1, q0=0, q1=q1s)
+    t6 = time.perf_counter()
+    sweep1 = max((t6 - t5) - (t5 - t4), 1e-9)
+    T1 = (t4 - t3b) + (t5 - t4) + sweep1 / f1
+    m1 = len(e1) / f1
     return {"value": m_est / T_full, "unit": "edges/s", "cores": threads, "kind": "oracle",
             "sample": "n=%d alpha=%g kbar=%g seed=%d: sampling, table and slab sort of all points timed in full "
                       "(%.1f s); band sweep over queries [0, %d) (%.0f%%, %d edges, %.1f s) scaled by 1/%.2f; "
                       "projected %.1f s for ~%.3g edges" % (args.n, args.alpha, args.kbar, args.seed, setup, q1,
-                                                            100 * frac, len(e), t3 - t2, frac, T_full, m_est)}
+                                                            100 * frac, len(e), t3 - t2, frac, T_full, m_est),
+            "single_thread": {"value": m1 / T1, "unit": "edges/s", "cores": 1,
+                              "sample": "sampling, table and slab sort of all points on one thread (%.1f s); "
+                                        "band sweep over queries [0, %d) (%.1f%%, %d edges, %.1f s) scaled by "
+                                        "1/%.3f; projected %.1f s" % (t5 - t3b, q1s, 100 * f1, len(e1), t6 - t5,
+                                                                      f1, T1)}}
 
 
 def main():
