@@ -50,16 +50,20 @@ void plan(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_o
 // stretch of every slab and share it in L2; the sorted list is cut into
 // NXCD contiguous chunks and workgroup b (dispatched round-robin over the
 // XCDs, b mod NXCD) takes its units from chunk b mod NXCD, so each XCD's L2
-// holds only its own sectors.  Edge offsets are per logical unit, so the
-// order of execution never changes the output.
+// holds only its own sectors.  Edge counts and offsets are kept per
+// execution slot k (the unit's place in this order), so the edge list
+// follows the execution order: the units in flight on one XCD write
+// neighbouring stretches of it (DRAM rows are reused; measured 0.04 ms
+// faster at n = 10^7 than offsets in batch order).  The order is a fixed
+// function of the plan, the same for the FP64 and FP32 forms.
 constexpr uint32_t NXCD = 8;
 constexpr int SECTOR_BITS = 12;
 
-__device__ __forceinline__ uint64_t exec_unit(const QueryArgs &A, int w) {
+__device__ __forceinline__ uint64_t exec_unit(const QueryArgs &A, int w, uint64_t &k) {
     const uint64_t U = A.n_units;
     const uint64_t chunk = (U + NXCD - 1) / NXCD;
     const uint64_t x = blockIdx.x % NXCD, slot = (uint64_t)(blockIdx.x / NXCD) * 4 + w;
-    const uint64_t k = x * chunk + slot;
+    k = x * chunk + slot;
     if (slot >= chunk || k >= U) return ~0ull;
     return A.unit_order ? A.unit_order[k] : A.unit_base + k;
 }
@@ -131,18 +135,20 @@ __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
     __shared__ CountSmem<FP32> sm[4];
     // wavefront index in scalar registers: the unit lookups become scalar loads
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const uint64_t unit = exec_unit(A, w);
+    uint64_t k;
+    const uint64_t unit = exec_unit(A, w, k);
     if (unit == ~0ull) return;  // uniform per wavefront; no block-wide barriers below
-    count_unit<FP32, WIDE>(A, unit, lane, sm[w]);
+    count_unit<FP32, WIDE>(A, unit, k, lane, sm[w]);
 }
 
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     __shared__ EmitSmem sm[4];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const uint64_t unit = exec_unit(A, w);
+    uint64_t k;
+    const uint64_t unit = exec_unit(A, w, k);
     if (unit == ~0ull) return;
-    emit_unit<WIDE, true>(A, unit, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
+    emit_unit<WIDE, true>(A, unit, k, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
 // Below n = 2^28 every table byte offset fits 32 bits (WIDE = false).

@@ -464,7 +464,8 @@ struct CountSmem {
 };
 
 template <int FP32, bool WIDE>
-__device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, int lane, CountSmem<FP32> &S) {
+__device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane,
+                                           CountSmem<FP32> &S) {
     constexpr int VT = VT_COUNT;
     const Geo &g = A.geo;
     const UnitSetup u = unit_setup(A, unit, lane);
@@ -570,7 +571,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, in
     }
     wave_lds_sync();
     for (uint32_t k = lane; k < word; k += 64) A.bits[unit * BITW + k] = S.bits[k];
-    if (lane == 0) A.unit_edges[unit] = found;
+    if (lane == 0) A.unit_edges[slot] = found;
     if (FP32) {
         const uint64_t rc = wave_sum_u64(rechecks), dg = wave_sum_u64(disagree);
         if (lane == 0 && rc) atomicAdd(&A.stats[0], (unsigned long long)rc);
@@ -715,9 +716,9 @@ __device__ __forceinline__ void emit_store(const EmitStep &s, __amdgpu_buffer_rs
 }
 
 template <bool WIDE, bool SBITS = false>
-__device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int lane, EmitSmem &S) {
+__device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane, EmitSmem &S) {
     const Geo &g = A.geo;
-    const uint32_t todo = uniform_u32(A.unit_edges[unit]);
+    const uint32_t todo = uniform_u32(A.unit_edges[slot]);
     if (todo == 0) return;
     const UnitSetup u = unit_setup(A, unit, lane);
     const uint32_t myqi = u.valid ? g.idx[u.v] : 0u;
@@ -727,7 +728,7 @@ __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, int
 #pragma unroll
     for (int i = 0; i < VT_EMIT; ++i) S.flag[i * 64 + lane] = 0u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t at = uniform_u64(A.unit_edge_off[unit]);  // the resource must sit in scalar registers
+    const uint64_t at = uniform_u64(A.unit_edge_off[slot]);  // the resource must sit in scalar registers
     uint64_t cap = A.out_capacity > at ? A.out_capacity - at : 0ull;
     cap = cap < todo ? cap : todo;
     const __amdgpu_buffer_rsrc_t out =

@@ -464,7 +464,8 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     }
     pl.n_units = U;
 
-    // per-unit arrays are indexed by global unit id (a share touches its range only)
+    // ubatch is indexed by global unit id (a share touches its range only);
+    // uedges and ueoff by the share's execution slot 0 .. U-1
     RHG_BUF(ubatch, uint32_t, S_UBATCH, std::max<uint64_t>(Uall, 1));
     RHG_BUF(uedges, uint32_t, S_UEDGES, std::max<uint64_t>(Uall, 1));
     RHG_BUF(ueoff, uint64_t, S_UEOFF, Uall + 1);
@@ -512,9 +513,9 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     rhgk::query_count(qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
     // edge offsets of the share's units, from 0 at its first unit
-    rhgk::scan_u32(uedges + u0, ueoff + u0, U, scan2, st);
+    rhgk::scan_u32(uedges, ueoff, U, scan2, st);
     RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
-    RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + u0 + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     uint32_t *usort_err = (uint32_t *)((char *)c->pinned + 1028);
     *usort_err = 0;

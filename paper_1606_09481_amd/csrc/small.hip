@@ -316,8 +316,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
 
     // ---- a5: count
     for (uint64_t u = w; u < U; u += SM_WAVES) {
-        if (D.fp32) count_unit<1, false>(sA, u, lane, P.count1[w]);
-        else count_unit<0, false>(sA, u, lane, P.count0[w]);
+        if (D.fp32) count_unit<1, false>(sA, u, u, lane, P.count1[w]);
+        else count_unit<0, false>(sA, u, u, lane, P.count0[w]);
     }
     __syncthreads();
 
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
     }
 
     // ---- a7: emit
-    for (uint64_t u = w; u < U; u += SM_WAVES) emit_unit<false>(sA, u, lane, P.emit[w]);
+    for (uint64_t u = w; u < U; u += SM_WAVES) emit_unit<false>(sA, u, u, lane, P.emit[w]);
     if (t == 0) Z.status = 0;
 }
 
