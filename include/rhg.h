@@ -199,9 +199,36 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
  * The arrays are owned by the caller and must not
  * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
  * finite and positive; RHG_ERANGE: n >= 2^31.  Regenerate the graph of the moved points with
- * rhg_generate_from_coords (coords_on_device = 1). */
+ * rhg_generate_from_coords (coords_on_device = 1), or update it with
+ * rhg_update_after_move. */
 rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,
                     const double *tau_phi, double *tau_r);
+
+/* Dynamic model (Sec. III-C): the graph after a move, updated from the graph
+ * before it instead of generated anew.  An edge between two points that did
+ * not move is still an edge; every edge at a moved point is found by the band
+ * query of the moved points alone, in every slab and both directions (the
+ * window bound of Sec. III-B holds for slabs below the query's too), a pair
+ * of two moved points being taken once.
+ *   theta[n], r[n]   device FP64 coordinates after the move; read only.
+ *   moved[n]         device bytes, original order: nonzero for every point
+ *                    whose coordinates changed (points may be flagged that
+ *                    did not move; they are queried again); read only.
+ *   old_pairs        device int32 pairs (2 * m_old), the edge list of the
+ *                    same n points before the move, each edge once, any
+ *                    order; read only.
+ * *out is a graph as rhg_generate_from_coords returns, with library-owned
+ * edges: the old pairs whose ends both stayed, in their old order, then the
+ * pairs at moved points.  If old_pairs is the threshold graph of the
+ * coordinates before the move and moved covers every point that moved, its
+ * edge set is that of rhg_generate_from_coords(theta, r), the same bits of
+ * the same distance test deciding every pair.  The arrays must stay valid
+ * until the call returns.  RHG_EINVAL: null arrays, a pair naming a point
+ * outside 0..n-1, or a query share set on the context; other errors as for
+ * rhg_generate_from_coords. */
+rhg_status rhg_update_after_move(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r, double R,
+                                 rhg_precision precision, const uint8_t *moved, const int32_t *old_pairs,
+                                 uint64_t m_old, rhg_graph **out);
 
 /* Two-phase form for caller-owned output (e.g. a PyTorch tensor):
  * rhg_count plans and counts (m), rhg_emit writes the m pairs into

@@ -54,3 +54,106 @@ void move(uint64_t n, double alpha, double R, double S, double *theta, double *r
 }
 
 }  // namespace rhgk
+
+// ---------------------------------------------------------------------------
+// Graph update after a move.  The edges between two points that did not move
+// are still edges; every edge at a moved point is found again by the band
+// query of the moved points (Geo::moved).  The old list is compacted in its
+// own order: tiles of KEEP_TILE pairs, a per-tile count, an exclusive scan of
+// the counts, then each tile writes its kept pairs in order.
+// ---------------------------------------------------------------------------
+namespace rhgk {
+using namespace rhgd;
+
+__global__ __launch_bounds__(256) void k_moved_sorted(const uint32_t *idx, const uint8_t *moved, uint32_t n,
+                                                      uint8_t *out) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) out[s] = moved[idx[s]] != 0 ? 1 : 0;
+}
+
+void moved_sorted(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint8_t *out, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_moved_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, moved, (uint32_t)n,
+                       out);
+}
+
+constexpr int KEEP_ITEMS = 16;
+constexpr uint64_t KEEP_TILE = 256 * KEEP_ITEMS;
+
+// Pair k is kept iff both ends are points 0..n-1 that did not move; an end
+// outside 0..n-1 raises *err and drops the pair (so no read leaves moved[]).
+__device__ __forceinline__ bool keep_pair(const int2 *pairs, uint64_t m, uint64_t k, const uint8_t *moved, uint32_t n,
+                                          uint32_t *err) {
+    if (k >= m) return false;
+    const int2 e = pairs[k];
+    const uint32_t a = (uint32_t)e.x, b = (uint32_t)e.y;
+    if (a >= n || b >= n) {
+        atomicOr(err, 1u);
+        return false;
+    }
+    return moved[a] == 0 && moved[b] == 0;
+}
+
+__global__ __launch_bounds__(256) void k_keep_count(const int2 *pairs, uint64_t m, const uint8_t *moved, uint32_t n,
+                                                    uint32_t *counts, uint32_t *err) {
+    __shared__ uint32_t wsum[4];
+    const uint64_t base = (uint64_t)blockIdx.x * KEEP_TILE;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < KEEP_ITEMS; ++i) c += keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, err) ? 1u : 0u;
+    c = (uint32_t)wave_sum_u64(c);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Tile order: item i of thread t is pair base + 256 i + t; a pair's place
+// among the tile's kept pairs counts those of earlier items, then of lower
+// threads of the same item (per-wave ballots, then the waves before).
+__global__ __launch_bounds__(256) void k_keep_write(const int2 *pairs, uint64_t m, const uint8_t *moved, uint32_t n,
+                                                    const uint64_t *offs, int2 *out, uint32_t *err) {
+    __shared__ uint32_t wcnt[KEEP_ITEMS][4];
+    const uint64_t base = (uint64_t)blockIdx.x * KEEP_TILE;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool kp[KEEP_ITEMS];
+    uint32_t below[KEEP_ITEMS];
+#pragma unroll
+    for (int i = 0; i < KEEP_ITEMS; ++i) {
+        kp[i] = keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, err);
+        const uint64_t bal = __ballot(kp[i]);
+        below[i] = (uint32_t)__popcll(bal & lt);
+        if (lane == 0) wcnt[i][w] = (uint32_t)__popcll(bal);
+    }
+    __syncthreads();
+    uint64_t at = offs[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < KEEP_ITEMS; ++i) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            before += q < w ? wcnt[i][q] : 0u;
+            all += wcnt[i][q];
+        }
+        if (kp[i]) out[at + before + below[i]] = pairs[base + i * 256 + threadIdx.x];
+        at += all;
+    }
+}
+
+void keep_count(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,
+                hipStream_t st) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_keep_count, dim3((unsigned)((m + KEEP_TILE - 1) / KEEP_TILE)), dim3(256), 0, st, pairs, m,
+                       moved, (uint32_t)n, counts, err);
+}
+
+void keep_write(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, const uint64_t *offs, int2 *out,
+                uint32_t *err, hipStream_t st) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_keep_write, dim3((unsigned)((m + KEEP_TILE - 1) / KEEP_TILE)), dim3(256), 0, st, pairs, m,
+                       moved, (uint32_t)n, offs, out, err);
+}
+
+uint64_t keep_tiles(uint64_t m) { return (m + KEEP_TILE - 1) / KEEP_TILE; }
+
+}  // namespace rhgk

@@ -34,15 +34,19 @@
 namespace rhgk {
 using namespace rhgd;
 
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_plan(Geo g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off) {
     const uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (b >= (g.n + 63) / 64) return;  // whole wavefronts past the last batch
-    plan_batch(g, win, batch_cand, batch_slab_off, b, threadIdx.x & 63);
+    plan_batch<FULL>(g, win, batch_cand, batch_slab_off, b, threadIdx.x & 63);
 }
 
 void plan(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off, hipStream_t st) {
     if (!g.n) return;
-    hipLaunchKernelGGL(k_plan, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
+    if (g.slab_mask == 0u)
+        hipLaunchKernelGGL(k_plan<true>, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
+    else
+        hipLaunchKernelGGL(k_plan<false>, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
 }
 
 // Execution order of units.  Units are executed grouped by the angular
@@ -130,15 +134,15 @@ void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_t
     radix_sort(key, id, key_tmp, id_tmp, sort_scratch, a.n_units, SECTOR_BITS, st);
 }
 
-template <int FP32, bool WIDE>
+template <int FP32, bool WIDE, bool FULL>
 __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
-    __shared__ CountSmem<FP32> sm[4];
+    __shared__ CountSmem<FP32, FULL> sm[4];
     // wavefront index in scalar registers: the unit lookups become scalar loads
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     uint64_t k;
     const uint64_t unit = exec_unit(A, w, k);
     if (unit == ~0ull) return;  // uniform per wavefront; no block-wide barriers below
-    count_unit<FP32, WIDE>(A, unit, k, lane, sm[w]);
+    count_unit<FP32, WIDE, FULL>(A, unit, k, lane, sm[w]);
 }
 
 template <bool WIDE>
@@ -151,17 +155,23 @@ __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     emit_unit<WIDE, true>(A, unit, k, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
+template <int FP32, bool FULL>
+static void launch_count(const QueryArgs &a, hipStream_t st) {
+    const dim3 grid(exec_blocks(a.n_units)), block(256);
+    if (a.geo.n >= (1u << 28)) hipLaunchKernelGGL((k_count<FP32, true, FULL>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_count<FP32, false, FULL>), grid, block, 0, st, a);
+}
+
 // Below n = 2^28 every table byte offset fits 32 bits (WIDE = false).
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {
     if (!a.n_units) return;
-    const bool wide = a.geo.n >= (1u << 28);
-    const dim3 grid(exec_blocks(a.n_units)), block(256);
+    const bool full = a.geo.moved != nullptr;
     if (fp32) {
-        if (wide) hipLaunchKernelGGL((k_count<1, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_count<1, false>), grid, block, 0, st, a);
+        if (full) launch_count<1, true>(a, st);
+        else launch_count<1, false>(a, st);
     } else {
-        if (wide) hipLaunchKernelGGL((k_count<0, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_count<0, false>), grid, block, 0, st, a);
+        if (full) launch_count<0, true>(a, st);
+        else launch_count<0, false>(a, st);
     }
 }
 

@@ -79,13 +79,19 @@ __device__ __forceinline__ uint2 range_pos(const Geo &g, int j, uint32_t xlo, ui
     return make_uint2(l0, h0);
 }
 
-// Circular window (start, count) of sorted query s (slab i) in slab j >= i.
-__device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j, double thv, uint32_t qv) {
+// Circular window (start, count) of sorted query s (slab i) in slab j: the
+// forward range of the own-slab rule when fwd (j == i), else the two-sided
+// range.  The bound with c_j holds for a slab j below the query's too: the
+// largest sin^2 of the half-angle allowed at distance R,
+// (K - cosh(r_v - x)) / (2 sinh r_v sinh x), decreases in the candidate's
+// radius x for every x when r_v <= R (its derivative has the sign of
+// cosh r_v - K cosh x), so over slab j it is largest at x = c_j.
+__device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j, double thv, uint32_t qv, bool fwd) {
     const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
     if (nj == 0) return make_uint2(bs, 0u);
     double delta = 0.0;
     const int whole = (j == 0) ? 1 : half_width(g, qp, j, &delta);
-    if (j == i) {
+    if (fwd) {
         // forward range from s + 1 to the first position with key >= t (a key
         // "> x" is one ">= x + 1"), past the slab end when it wraps; one
         // search for all four cases (whole slab or not, wrapping or not)
@@ -109,6 +115,8 @@ __device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j,
 // at win[winbase[j] + v], so the 64 queries of a batch read one slab's
 // windows with one coalesced load.
 // One wavefront plans one batch b of 64 sorted queries (lane = query b*64+lane).
+// FULL: update mode (Geo::moved; the caller checks g.slab_mask == 0).
+template <bool FULL = false>
 __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off,
                                            uint32_t b, int lane) {
     // b and the slab index are wave-uniform: kept in scalar registers, the
@@ -117,7 +125,8 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
     b = uniform_u32(b);
     const uint32_t s = b * BATCH + (uint32_t)lane;
     const bool valid = s < g.n;
-    const int jmin = (int)uniform_u32(g.keys[b * BATCH] >> QBITS);
+    constexpr bool full = FULL;  // update mode: moved queries, every slab
+    const int jmin = full ? 0 : (int)uniform_u32(g.keys[b * BATCH] >> QBITS);
     int i = g.B;
     uint32_t qv = 0;
     double thv = 0.0;
@@ -133,14 +142,16 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
         qp.hem = 0.5 * e.y;
         qp.inv2sh = (shv > 0.0) ? 1.0 / (2.0 * shv) : 0.0;
     }
+    const bool asks = valid && (!full || g.moved[s] != 0);
+    const int ifirst = full ? 0 : i;  // first slab with a window
     uint64_t *row = batch_slab_off + (uint64_t)b * (g.B + 1);
     for (int j = lane; j <= jmin && j <= g.B; j += 64) row[j] = 0;
     uint64_t acc = 0;
     const bool small = 64ull * g.n < (1ull << 32);
     for (int j = jmin; j < g.B; ++j) {
         uint32_t cnt = 0;
-        if (valid && j >= i) {
-            const uint2 x = window(g, qp, s, i, j, thv, qv);
+        if (valid && j >= ifirst) {
+            const uint2 x = asks ? window(g, qp, s, i, j, thv, qv, !full && j == i) : make_uint2(0u, 0u);
             win[g.winbase[j] + s] = x;
             cnt = x.y;
         }
@@ -258,8 +269,9 @@ __device__ __forceinline__ UnitSetup unit_setup_chain(const QueryArgs &A, uint64
     u.r1 = (u.r0 + UNIT < bc) ? u.r0 + UNIT : bc;
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
-    u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
-    const int jmin = (int)uniform_u32(g.keys[u.b * BATCH] >> QBITS);
+    // first slab with windows: the query's own, or slab 0 in update mode
+    u.iv = u.valid ? (int)((g.keys[u.v] >> QBITS) & g.slab_mask) : g.B;
+    const int jmin = (int)uniform_u32((g.keys[u.b * BATCH] >> QBITS) & g.slab_mask);
     // segments of slabs jmin..B-1 end at row[j+1] (row[jmin] = 0)
     const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
     const int k = jmin + lane;
@@ -290,7 +302,7 @@ __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t uni
     u.r1 = d.r1;
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
-    u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
+    u.iv = u.valid ? (int)((g.keys[u.v] >> QBITS) & g.slab_mask) : g.B;
     // segment starts: rlo of lane k = row[jmin + k] (row[jmin] = 0)
     const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
     const int k = u.jmin + lane;
@@ -453,7 +465,7 @@ __device__ __forceinline__ uint32_t position_pb(uint32_t pb, uint32_t t, uint32_
 // Per-wavefront LDS of the count pass.
 // (FP32 operands only in the filter form, to keep the FP64 form's LDS, and
 // with it the workgroups per CU, down.)
-template <int FP32>
+template <int FP32, bool FULL = false>
 struct CountSmem {
     uint32_t pb[64];    // per rank: start position - flattened offset
     uint8_t flag[64 * VT_COUNT];
@@ -461,11 +473,15 @@ struct CountSmem {
     float qf[FP32 ? 3 : 1][64];
     unsigned long long bits[BITW];
     uint2 wpre[SEG_PRE][64];
+    uint32_t qpos[FULL ? 64 : 1];  // per rank: the query's sorted position (update mode)
 };
 
-template <int FP32, bool WIDE>
+// FULL: update mode (Geo::moved): a candidate that passes the distance test
+// is an edge unless it is the query itself, or a moved point that comes
+// before the query in sorted order (that pair is the other query's).
+template <int FP32, bool WIDE, bool FULL = false>
 __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane,
-                                           CountSmem<FP32> &S) {
+                                           CountSmem<FP32, FULL> &S) {
     constexpr int VT = VT_COUNT;
     const Geo &g = A.geo;
     const UnitSetup u = unit_setup(A, unit, lane);
@@ -512,6 +528,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
             S.qd[2][rk] = mine.sh2;
             S.qd[3][rk] = mine.hs;
             S.qd[4][rk] = mine.hc;
+            if (FULL) S.qpos[rk] = u.v;
             if (FP32) {
                 S.qf[0][rk] = mine.hep32;
                 S.qf[1][rk] = mine.hem32;
@@ -557,7 +574,11 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 // FP64: lanes past the end skip the test (measured faster there)
                 const uint32_t r = FP32 ? (edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) & (act[i] ? 7u : 0u))
                                         : (act[i] ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
-                const int flag = (int)(r & 1u);
+                int flag = (int)(r & 1u);
+                if (FULL) {
+                    const uint32_t qp = S.qpos[rk[i]];
+                    flag &= (p[i] != qp && (g.moved[p[i]] == 0 || p[i] > qp)) ? 1 : 0;
+                }
                 if (FP32) {
                     rechecks += (r >> 1) & 1u;
                     disagree += (r >> 2) & 1u;

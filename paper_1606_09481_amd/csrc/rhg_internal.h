@@ -17,7 +17,7 @@ enum Slot {
     S_TH, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
-    S_SHARD, S_UDESC,
+    S_SHARD, S_UDESC, S_MOVED, S_KEEPC, S_KEEPO, S_KEEPERR, S_SCANSCR3,
     S_COUNT
 };
 
@@ -60,6 +60,11 @@ struct Request {
     double band_ratio = 0.0;
     const double *theta = nullptr, *r = nullptr, *table = nullptr;
     int on_device = 0;
+    // graph update after a move (device): per-point moved flags in original
+    // order, and the edge list before the move
+    const uint8_t *moved = nullptr;
+    const int32_t *old_pairs = nullptr;
+    uint64_t m_old = 0;
 };
 
 // One planned generation.
@@ -77,6 +82,13 @@ struct Plan {
     bool emitted = false;
     double ms[8] = {};
     double count_kernel_ms = 0;  // the count kernel alone (ms[4] also holds unit bookkeeping and order)
+    // graph update: the old pairs kept (m_keep, written first, by the tile
+    // offsets keep_off), then the m - m_keep pairs at moved points
+    const int2 *old_pairs = nullptr;
+    const uint8_t *moved_orig = nullptr;
+    uint64_t m_old = 0, m_keep = 0;
+    const uint64_t *keep_off = nullptr;
+    uint32_t *keep_err = nullptr;
 };
 
 struct Graph {

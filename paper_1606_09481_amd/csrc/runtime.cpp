@@ -311,6 +311,7 @@ static float round_up_f32(double x) {
 // the FP32 filter thresholds.
 void geo_static(const Plan &pl, Geo &g) {
     std::memset(&g, 0, sizeof(Geo));
+    g.slab_mask = ~0u;
     g.n = (uint32_t)pl.n;
     g.B = pl.B;
     g.R = pl.R;
@@ -385,6 +386,14 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         if (!f32) return RHG_ENOMEM;
     }
     rhgk::gather(src, vals, n, th, epm, sh, hsc, f32, st);
+    const bool update = rq.moved != nullptr;
+    uint8_t *msorted = nullptr;
+    if (update) {
+        if (S > 1) return RHG_EINVAL;  // an update is one whole graph
+        msorted = (uint8_t *)c->buf(S_MOVED, n);
+        if (!msorted) return RHG_ENOMEM;
+        rhgk::moved_sorted(vals, rq.moved, n, msorted, st);
+    }
     RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
 
     // slab sizes -> layout of windows and bucket index
@@ -405,7 +414,9 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         g.bs[j] = hh[j];
         g.winbase[j] = wins;
         const uint32_t nj = hh[j + 1] - hh[j];
-        wins += hh[j + 1];  // queries of slabs <= j each have a window in slab j
+        // queries of slabs <= j each have a window in slab j (in an update
+        // every query has one in every slab)
+        wins += update ? n : hh[j + 1];
         int bits = std::max(0, std::min(24, ceil_log2(nj) - 1));
         g.bshift[j] = QBITS - bits;
         g.bto[j] = (uint32_t)btab_len;
@@ -424,6 +435,8 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.hsc = hsc;
     g.f32 = f32;
     g.btab = btab;
+    g.moved = msorted;
+    g.slab_mask = update ? 0u : ~0u;
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     rhgk::bucket_index(g, btab, st);
 
@@ -514,6 +527,31 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipEventRecord(c->ev[EV_COUNT1], st));
     // edge offsets of the share's units, from 0 at its first unit
     rhgk::scan_u32(uedges, ueoff, U, scan2, st);
+    // an update keeps the old pairs whose ends both stayed: per-tile counts and offsets
+    pl.old_pairs = nullptr;
+    pl.keep_off = nullptr;
+    pl.m_old = pl.m_keep = 0;
+    pin[6] = 0;
+    uint32_t *keep_err_host = (uint32_t *)((char *)c->pinned + 1032);
+    *keep_err_host = 0;
+    if (update && rq.m_old) {
+        const uint64_t tiles = rhgk::keep_tiles(rq.m_old);
+        RHG_BUF(kcnt, uint32_t, S_KEEPC, tiles);
+        RHG_BUF(koff, uint64_t, S_KEEPO, tiles + 1);
+        RHG_BUF(kerr, uint32_t, S_KEEPERR, 1);
+        void *scan3 = c->buf(S_SCANSCR3, rhgk::scan_scratch_bytes(tiles));
+        if (!scan3) return RHG_ENOMEM;
+        RHG_HIP(hipMemsetAsync(kerr, 0, sizeof(uint32_t), st));
+        rhgk::keep_count((const int2 *)rq.old_pairs, rq.m_old, rq.moved, n, kcnt, kerr, st);
+        rhgk::scan_u32(kcnt, koff, tiles, scan3, st);
+        RHG_HIP(hipMemcpyAsync(pin + 6, koff + tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        RHG_HIP(hipMemcpyAsync(keep_err_host, kerr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        pl.old_pairs = (const int2 *)rq.old_pairs;
+        pl.moved_orig = rq.moved;
+        pl.m_old = rq.m_old;
+        pl.keep_off = koff;
+        pl.keep_err = kerr;
+    }
     RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
     RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -524,7 +562,9 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_HIP(hipStreamSynchronize(st));
     RHG_HIP(hipGetLastError());
     if (*usort_err != 0) return RHG_EDEVICE;
-    pl.m = pin[2];
+    if (*keep_err_host != 0) return RHG_EINVAL;  // an old pair names a point outside 0..n-1
+    pl.m_keep = pin[6];
+    pl.m = pin[2] + pl.m_keep;
     pl.rechecks = pin[3];
     pl.disagreements = pin[4];
     return RHG_OK;
@@ -535,9 +575,12 @@ rhg_status run_emit(Ctx *c, Plan &pl, int2 *out) {
     RHG_HIP(hipSetDevice(c->device));
     (void)hipGetLastError();
     const hipStream_t st = c->stream;
-    pl.qa.out = out;
-    pl.qa.out_capacity = pl.m;
+    // an update writes the kept old pairs first, the pairs at moved points after them
+    pl.qa.out = out + pl.m_keep;
+    pl.qa.out_capacity = pl.m - pl.m_keep;
     RHG_HIP(hipEventRecord(c->ev[EV_EMIT0], st));
+    if (pl.keep_off)
+        rhgk::keep_write(pl.old_pairs, pl.m_old, pl.moved_orig, pl.n, pl.keep_off, out, pl.keep_err, st);
     rhgk::query_emit(pl.qa, pl.fp32, st);
     RHG_HIP(hipEventRecord(c->ev[EV_EMIT1], st));
     RHG_HIP(hipStreamSynchronize(st));
@@ -714,6 +757,22 @@ extern "C" rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const do
     Request rq;
     rhg_status s = coords_request(n, theta, r, table5xn, R, precision, on_device, rq);
     if (s != RHG_OK || !out) return s != RHG_OK ? s : RHG_EINVAL;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_update_after_move(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r, double R,
+                                            rhg_precision precision, const uint8_t *moved, const int32_t *old_pairs,
+                                            uint64_t m_old, rhg_graph **out) {
+    if (!out || !moved || (m_old && !old_pairs)) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = coords_request(n, theta, r, nullptr, R, precision, 1, rq);
+    if (s != RHG_OK) return s;
+    rq.moved = moved;
+    rq.old_pairs = old_pairs;
+    rq.m_old = m_old;
     Graph *g = nullptr;
     s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
     if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);

@@ -97,6 +97,7 @@ def load(path: Optional[str] = None):
         "rhg_generate_from_coords": (i32, [vp, u64, vp, vp, d, i32, i32, P(vp)]),
         "rhg_generate_from_table": (i32, [vp, u64, vp, vp, vp, d, i32, i32, P(vp)]),
         "rhg_move": (i32, [vp, u64, d, d, vp, vp, vp, vp]),
+        "rhg_update_after_move": (i32, [vp, u64, vp, vp, d, i32, vp, vp, u64, P(vp)]),
         "rhg_count": (i32, [vp, P(rhg_params), P(vp), P(u64)]),
         "rhg_emit": (i32, [vp, vp, vp, u64]),
         "rhg_graph_num_edges": (i32, [vp, P(u64)]),
@@ -239,6 +240,25 @@ def rhg_move(ctx, theta, r, tau_phi, tau_r, alpha: float, R: float):
             raise ValueError("rhg_move: arrays of different lengths")
     _check(load().rhg_move(ctx, n, float(alpha), float(R), _ptr(theta), _ptr(r), _ptr(tau_phi), _ptr(tau_r)),
            "rhg_move")
+
+
+def rhg_update_after_move(ctx, theta, r, R: float, moved, old_pairs, m_old: int,
+                          precision: int = RHG_FP64) -> ctypes.c_void_p:
+    """Graph after a move from the graph before it.  theta, r: float64 torch
+    tensors on the GPU (coordinates after the move); moved: uint8 tensor on
+    the GPU, nonzero for moved points (original order); old_pairs: int32
+    device tensor (or device address) holding the m_old pairs of the graph
+    before the move."""
+    n = int(theta.numel())
+    for x in (r, moved):
+        if int(x.numel()) != n:
+            raise ValueError("rhg_update_after_move: arrays of different lengths")
+    if not isinstance(old_pairs, int) and int(old_pairs.numel()) < 2 * int(m_old):
+        raise ValueError("rhg_update_after_move: old_pairs holds fewer than m_old pairs")
+    g = ctypes.c_void_p()
+    _check(load().rhg_update_after_move(ctx, n, _ptr(theta), _ptr(r), float(R), int(precision), _ptr(moved),
+                                        _ptr(old_pairs), int(m_old), ctypes.byref(g)), "rhg_update_after_move")
+    return g
 
 
 def rhg_count(ctx, p: rhg_params) -> Tuple[ctypes.c_void_p, int]:
