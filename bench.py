@@ -155,8 +155,9 @@ def run_shares(args):
 def run_dynamic(args):
     """Dynamic model (Sec. III-C) at the benchmark size: one movement step of
     all nodes and of 12% of them (tau_phi in (-1, 1), tau_r in (-10, 1), the
-    paper's ranges), timed with HIP events on the context stream, then the
-    graph of the moved points regenerated from the device arrays."""
+    paper's ranges), timed with HIP events on the context stream; then one
+    more 12% move, whose graph is both updated from the graph before it and
+    regenerated from the device arrays."""
     import torch
     from paper_1606_09481_amd import rhg
 
@@ -188,19 +189,46 @@ def run_dynamic(args):
             t = sum(times) / len(times)
             gbs = 48.0 * n / (t * 1e-3) / 1e9  # read theta, r, tau_phi, tau_r; write theta, r
             res["move_all" if frac == 1.0 else "move_12pct"] = {"ms": t, "GB_s": gbs, "frac_of_hbm_peak": gbs / 8000.0}
-        gen = []
+        # the graph before one more 12% move, then the graph after it: updated
+        # (rhg_update_after_move) and regenerated (rhg_generate_from_coords)
+        g0 = rhg.rhg_generate_from_coords(ctx, th, r, R)
+        m0 = rhg.rhg_graph_num_edges(g0)
+        old = rhg.rhg_graph_edges_device(g0)
+        sel = torch.rand(n, device="cuda", generator=g) < 0.12
+        tp = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 2 - 1, 0.0)
+        tr = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 11 - 10, 0.0)
+        moved = sel.to(torch.uint8)
+        rhg.rhg_move(ctx, th, r, tp, tr, alpha, R)
+        upd, gen = [], []
         for it in range(1 + 3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            gr = rhg.rhg_generate_from_coords(ctx, th, r, R)
+            gu = rhg.rhg_update_after_move(ctx, th, r, R, moved, old, m0)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
+            mu = rhg.rhg_graph_num_edges(gu)
+            st_u = rhg.rhg_graph_stats(gu)
+            rhg.rhg_graph_free(gu)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            gr = rhg.rhg_generate_from_coords(ctx, th, r, R)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
             m = rhg.rhg_graph_num_edges(gr)
             rhg.rhg_graph_free(gr)
             if it >= 1:
-                gen.append(t1 - t0)
+                upd.append(t1 - t0)
+                gen.append(t3 - t2)
+        rhg.rhg_graph_free(g0)
+        if mu != m:
+            raise RuntimeError("update after a move gave %d edges, regeneration %d" % (mu, m))
         res["regenerate"] = {"ms": 1e3 * sum(gen) / len(gen), "edges": m,
                              "what": "rhg_generate_from_coords on the moved device arrays (library-owned output)"}
+        res["update_12pct"] = {"ms": 1e3 * sum(upd) / len(upd), "edges": mu, "edges_before": m0,
+                               "moved": int(sel.sum().item()), "device_phases_ms": st_u.get("ms"),
+                               "speedup_vs_regenerate": sum(gen) / sum(upd),
+                               "what": "rhg_update_after_move from the graph before a move of 12% of the nodes "
+                                       "(library-owned output; same edge count as the regeneration)"}
     finally:
         rhg.rhg_ctx_destroy(ctx)
         del th, r, u

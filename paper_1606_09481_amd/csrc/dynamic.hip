@@ -65,15 +65,25 @@ void move(uint64_t n, double alpha, double R, double S, double *theta, double *r
 namespace rhgk {
 using namespace rhgd;
 
-__global__ __launch_bounds__(256) void k_moved_sorted(const uint32_t *idx, const uint8_t *moved, uint32_t n,
-                                                      uint8_t *out) {
+// Moved flags as bits (1.25 MB at n = 10^7, held in L2 by the random lookups
+// of the keep passes): bit s of out is moved[idx[s]] (moved[s] without idx).
+// One ballot per wavefront; out holds moved_bit_words(n) words.
+__global__ __launch_bounds__(256) void k_moved_bits(const uint32_t *idx, const uint8_t *moved, uint32_t n,
+                                                    uint32_t *out) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) out[s] = moved[idx[s]] != 0 ? 1 : 0;
+    const bool f = s < n && moved[idx ? idx[s] : s] != 0;
+    const uint64_t b = __ballot(f);
+    if ((threadIdx.x & 63) == 0) {
+        out[s >> 5] = (uint32_t)b;
+        out[(s >> 5) + 1] = (uint32_t)(b >> 32);
+    }
 }
 
-void moved_sorted(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint8_t *out, hipStream_t st) {
+uint64_t moved_bit_words(uint64_t n) { return (n + 255) / 256 * 8; }
+
+void moved_bits(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint32_t *out, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_moved_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, moved, (uint32_t)n,
+    hipLaunchKernelGGL(k_moved_bits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, moved, (uint32_t)n,
                        out);
 }
 
@@ -81,26 +91,31 @@ constexpr int KEEP_ITEMS = 16;
 constexpr uint64_t KEEP_TILE = 256 * KEEP_ITEMS;
 
 // Pair k is kept iff both ends are points 0..n-1 that did not move; an end
-// outside 0..n-1 raises *err and drops the pair (so no read leaves moved[]).
-__device__ __forceinline__ bool keep_pair(const int2 *pairs, uint64_t m, uint64_t k, const uint8_t *moved, uint32_t n,
-                                          uint32_t *err) {
-    if (k >= m) return false;
-    const int2 e = pairs[k];
+// outside 0..n-1 sets bad (the caller raises the error flag once) and drops
+// the pair, its lookups clamped into moved[].  No branch: the loads of a
+// thread's pairs, then of their flags, are all in flight together.
+__device__ __forceinline__ bool keep_pair(const int2 *pairs, uint64_t m, uint64_t k, const uint32_t *moved,
+                                          uint32_t n, bool &bad, int2 &e) {
+    const bool in = k < m;
+    e = pairs[in ? k : 0];
     const uint32_t a = (uint32_t)e.x, b = (uint32_t)e.y;
-    if (a >= n || b >= n) {
-        atomicOr(err, 1u);
-        return false;
-    }
-    return moved[a] == 0 && moved[b] == 0;
+    const bool ok = a < n && b < n;
+    bad |= in && !ok;
+    return in && ok && !bit_of(moved, min(a, n - 1u)) && !bit_of(moved, min(b, n - 1u));
 }
 
-__global__ __launch_bounds__(256) void k_keep_count(const int2 *pairs, uint64_t m, const uint8_t *moved, uint32_t n,
+__global__ __launch_bounds__(256) void k_keep_count(const int2 *pairs, uint64_t m, const uint32_t *moved, uint32_t n,
                                                     uint32_t *counts, uint32_t *err) {
     __shared__ uint32_t wsum[4];
     const uint64_t base = (uint64_t)blockIdx.x * KEEP_TILE;
     uint32_t c = 0;
+    bool bad = false;
 #pragma unroll
-    for (int i = 0; i < KEEP_ITEMS; ++i) c += keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, err) ? 1u : 0u;
+    for (int i = 0; i < KEEP_ITEMS; ++i) {
+        int2 e;
+        c += keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, bad, e) ? 1u : 0u;
+    }
+    if (bad) atomicOr(err, 1u);
     c = (uint32_t)wave_sum_u64(c);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -110,7 +125,7 @@ __global__ __launch_bounds__(256) void k_keep_count(const int2 *pairs, uint64_t 
 // Tile order: item i of thread t is pair base + 256 i + t; a pair's place
 // among the tile's kept pairs counts those of earlier items, then of lower
 // threads of the same item (per-wave ballots, then the waves before).
-__global__ __launch_bounds__(256) void k_keep_write(const int2 *pairs, uint64_t m, const uint8_t *moved, uint32_t n,
+__global__ __launch_bounds__(256) void k_keep_write(const int2 *pairs, uint64_t m, const uint32_t *moved, uint32_t n,
                                                     const uint64_t *offs, int2 *out, uint32_t *err) {
     __shared__ uint32_t wcnt[KEEP_ITEMS][4];
     const uint64_t base = (uint64_t)blockIdx.x * KEEP_TILE;
@@ -118,13 +133,16 @@ __global__ __launch_bounds__(256) void k_keep_write(const int2 *pairs, uint64_t 
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool kp[KEEP_ITEMS];
     uint32_t below[KEEP_ITEMS];
+    int2 e[KEEP_ITEMS];
+    bool bad = false;
 #pragma unroll
     for (int i = 0; i < KEEP_ITEMS; ++i) {
-        kp[i] = keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, err);
+        kp[i] = keep_pair(pairs, m, base + i * 256 + threadIdx.x, moved, n, bad, e[i]);
         const uint64_t bal = __ballot(kp[i]);
         below[i] = (uint32_t)__popcll(bal & lt);
         if (lane == 0) wcnt[i][w] = (uint32_t)__popcll(bal);
     }
+    if (bad) atomicOr(err, 1u);
     __syncthreads();
     uint64_t at = offs[blockIdx.x];
 #pragma unroll
@@ -135,19 +153,19 @@ __global__ __launch_bounds__(256) void k_keep_write(const int2 *pairs, uint64_t 
             before += q < w ? wcnt[i][q] : 0u;
             all += wcnt[i][q];
         }
-        if (kp[i]) out[at + before + below[i]] = pairs[base + i * 256 + threadIdx.x];
+        if (kp[i]) out[at + before + below[i]] = e[i];
         at += all;
     }
 }
 
-void keep_count(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,
+void keep_count(const int2 *pairs, uint64_t m, const uint32_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,
                 hipStream_t st) {
     if (!m) return;
     hipLaunchKernelGGL(k_keep_count, dim3((unsigned)((m + KEEP_TILE - 1) / KEEP_TILE)), dim3(256), 0, st, pairs, m,
                        moved, (uint32_t)n, counts, err);
 }
 
-void keep_write(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, const uint64_t *offs, int2 *out,
+void keep_write(const int2 *pairs, uint64_t m, const uint32_t *moved, uint64_t n, const uint64_t *offs, int2 *out,
                 uint32_t *err, hipStream_t st) {
     if (!m) return;
     hipLaunchKernelGGL(k_keep_write, dim3((unsigned)((m + KEEP_TILE - 1) / KEEP_TILE)), dim3(256), 0, st, pairs, m,

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_plan(Geo g, uint2 *win, uint64_t *batch
 
 void plan(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off, hipStream_t st) {
     if (!g.n) return;
-    if (g.slab_mask == 0u)
+    if (g.moved)
         hipLaunchKernelGGL(k_plan<true>, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
     else
         hipLaunchKernelGGL(k_plan<false>, dim3((g.n + 255) / 256), dim3(256), 0, st, g, win, batch_cand, batch_slab_off);
@@ -82,6 +82,7 @@ static unsigned exec_blocks(uint64_t U) {
 // batch, slab offsets, window, key) are interleaved, so that several are in
 // flight at once.
 constexpr int UKEY_UPW = 2;
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, uint32_t *id) {
     const Geo &g = A.geo;
     const int lane = threadIdx.x & 63;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) {
         const uint64_t unit = unit0 + q < A.n_units ? unit0 + q : A.n_units - 1;
-        u[q] = unit_setup_chain(A, A.unit_base + unit, lane);
+        u[q] = unit_setup_chain<FULL>(A, A.unit_base + unit, lane);
     }
 #pragma unroll
     for (int q = 0; q < UKEY_UPW; ++q) slab_windows(g, A, u[q], u[q].jstart, st[q], cnt[q], excl[q], tot[q]);
@@ -130,7 +131,9 @@ __global__ __launch_bounds__(256) void k_unit_key(QueryArgs A, uint32_t *key, ui
 void unit_order(const QueryArgs &a, uint32_t *key, uint32_t *id, uint32_t *key_tmp, uint32_t *id_tmp,
                 void *sort_scratch, hipStream_t st) {
     if (!a.n_units) return;
-    hipLaunchKernelGGL(k_unit_key, dim3((unsigned)((a.n_units + 4 * UKEY_UPW - 1) / (4 * UKEY_UPW))), dim3(256), 0, st, a, key, id);
+    const dim3 grid((unsigned)((a.n_units + 4 * UKEY_UPW - 1) / (4 * UKEY_UPW)));
+    if (a.geo.moved) hipLaunchKernelGGL(k_unit_key<true>, grid, dim3(256), 0, st, a, key, id);
+    else hipLaunchKernelGGL(k_unit_key<false>, grid, dim3(256), 0, st, a, key, id);
     radix_sort(key, id, key_tmp, id_tmp, sort_scratch, a.n_units, SECTOR_BITS, st);
 }
 
@@ -145,14 +148,14 @@ __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
     count_unit<FP32, WIDE, FULL>(A, unit, k, lane, sm[w]);
 }
 
-template <bool WIDE>
+template <bool WIDE, bool FULL>
 __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     __shared__ EmitSmem sm[4];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     uint64_t k;
     const uint64_t unit = exec_unit(A, w, k);
     if (unit == ~0ull) return;
-    emit_unit<WIDE, true>(A, unit, k, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
+    emit_unit<WIDE, true, FULL>(A, unit, k, lane, sm[w]);  // bitmaps from the count kernel: scalar loads
 }
 
 template <int FP32, bool FULL>
@@ -183,8 +186,14 @@ void query_emit(const QueryArgs &a, int fp32, hipStream_t st) {
     // faster at n = 10^7 (its early loads overlap the bitmap and offset reads)
     QueryArgs b = a;
     b.udesc = nullptr;
-    if (a.geo.n >= (1u << 28)) hipLaunchKernelGGL((k_emit<true>), grid, block, 0, st, b);
-    else hipLaunchKernelGGL((k_emit<false>), grid, block, 0, st, b);
+    const bool wide = a.geo.n >= (1u << 28), full = a.geo.moved != nullptr;
+    if (full) {
+        if (wide) hipLaunchKernelGGL((k_emit<true, true>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((k_emit<false, true>), grid, block, 0, st, b);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_emit<true, false>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((k_emit<false, false>), grid, block, 0, st, b);
+    }
 }
 
 }  // namespace rhgk

@@ -115,7 +115,8 @@ __device__ uint2 window(const Geo &g, const QPlan &qp, uint32_t s, int i, int j,
 // at win[winbase[j] + v], so the 64 queries of a batch read one slab's
 // windows with one coalesced load.
 // One wavefront plans one batch b of 64 sorted queries (lane = query b*64+lane).
-// FULL: update mode (Geo::moved; the caller checks g.slab_mask == 0).
+// FULL: update mode (Geo::moved): windows of the moved queries only, in every
+// slab, two-sided in their own slab as in the others.
 template <bool FULL = false>
 __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *batch_cand, uint64_t *batch_slab_off,
                                            uint32_t b, int lane) {
@@ -142,7 +143,7 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
         qp.hem = 0.5 * e.y;
         qp.inv2sh = (shv > 0.0) ? 1.0 / (2.0 * shv) : 0.0;
     }
-    const bool asks = valid && (!full || g.moved[s] != 0);
+    const bool asks = valid && (!full || bit_of(g.moved, s));
     const int ifirst = full ? 0 : i;  // first slab with a window
     uint64_t *row = batch_slab_off + (uint64_t)b * (g.B + 1);
     for (int j = lane; j <= jmin && j <= g.B; j += 64) row[j] = 0;
@@ -150,8 +151,10 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
     const bool small = 64ull * g.n < (1ull << 32);
     for (int j = jmin; j < g.B; ++j) {
         uint32_t cnt = 0;
-        if (valid && j >= ifirst) {
-            const uint2 x = asks ? window(g, qp, s, i, j, thv, qv, !full && j == i) : make_uint2(0u, 0u);
+        if (asks && j >= ifirst) {
+            // (an unmoved query of update mode has no window entries: its
+            // first slab is past the last, and its entries are never read)
+            const uint2 x = window(g, qp, s, i, j, thv, qv, !full && j == i);
             win[g.winbase[j] + s] = x;
             cnt = x.y;
         }
@@ -256,6 +259,8 @@ struct UnitSetup {
     uint64_t rlo, rhi;
 };
 
+// FULL: update mode; a moved query's windows start in slab 0, an unmoved one has none.
+template <bool FULL = false>
 __device__ __forceinline__ UnitSetup unit_setup_chain(const QueryArgs &A, uint64_t unit, int lane) {
     const Geo &g = A.geo;
     UnitSetup u;
@@ -269,9 +274,10 @@ __device__ __forceinline__ UnitSetup unit_setup_chain(const QueryArgs &A, uint64
     u.r1 = (u.r0 + UNIT < bc) ? u.r0 + UNIT : bc;
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
-    // first slab with windows: the query's own, or slab 0 in update mode
-    u.iv = u.valid ? (int)((g.keys[u.v] >> QBITS) & g.slab_mask) : g.B;
-    const int jmin = (int)uniform_u32((g.keys[u.b * BATCH] >> QBITS) & g.slab_mask);
+    // first slab with windows: the query's own (update mode: slab 0 if it moved)
+    if (FULL) u.iv = (u.valid && bit_of(g.moved, u.v)) ? 0 : g.B;
+    else u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
+    const int jmin = FULL ? 0 : (int)uniform_u32(g.keys[u.b * BATCH] >> QBITS);
     // segments of slabs jmin..B-1 end at row[j+1] (row[jmin] = 0)
     const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
     const int k = jmin + lane;
@@ -289,8 +295,9 @@ __device__ __forceinline__ UnitSetup unit_setup_chain(const QueryArgs &A, uint64
 // The same from the unit's descriptor: one scalar load, after which the
 // lane's loads (its query's key, the batch's segment offsets, the windows)
 // are all independent of each other, instead of a chain of dependent loads.
+template <bool FULL = false>
 __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t unit, int lane) {
-    if (!A.udesc) return unit_setup_chain(A, unit, lane);
+    if (!A.udesc) return unit_setup_chain<FULL>(A, unit, lane);
     const Geo &g = A.geo;
     UnitSetup u;
     unit = uniform_u64(unit);
@@ -302,7 +309,8 @@ __device__ __forceinline__ UnitSetup unit_setup(const QueryArgs &A, uint64_t uni
     u.r1 = d.r1;
     u.v = u.b * BATCH + lane;
     u.valid = u.v < g.n;
-    u.iv = u.valid ? (int)((g.keys[u.v] >> QBITS) & g.slab_mask) : g.B;
+    if (FULL) u.iv = (u.valid && bit_of(g.moved, u.v)) ? 0 : g.B;
+    else u.iv = u.valid ? (int)(g.keys[u.v] >> QBITS) : g.B;
     // segment starts: rlo of lane k = row[jmin + k] (row[jmin] = 0)
     const uint64_t *row = A.batch_slab_off + (uint64_t)u.b * (g.B + 1);
     const int k = u.jmin + lane;
@@ -484,7 +492,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                                            CountSmem<FP32, FULL> &S) {
     constexpr int VT = VT_COUNT;
     const Geo &g = A.geo;
-    const UnitSetup u = unit_setup(A, unit, lane);
+    const UnitSetup u = unit_setup<FULL>(A, unit, lane);
     Qv mine{};
     if (u.valid) {
         const double2 e = g.epm[u.v];
@@ -577,7 +585,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 int flag = (int)(r & 1u);
                 if (FULL) {
                     const uint32_t qp = S.qpos[rk[i]];
-                    flag &= (p[i] != qp && (g.moved[p[i]] == 0 || p[i] > qp)) ? 1 : 0;
+                    flag &= (p[i] != qp && (!bit_of(g.moved, p[i]) || p[i] > qp)) ? 1 : 0;
                 }
                 if (FP32) {
                     rechecks += (r >> 1) & 1u;
@@ -736,12 +744,12 @@ __device__ __forceinline__ void emit_store(const EmitStep &s, __amdgpu_buffer_rs
     }
 }
 
-template <bool WIDE, bool SBITS = false>
+template <bool WIDE, bool SBITS = false, bool FULL = false>
 __device__ __forceinline__ void emit_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane, EmitSmem &S) {
     const Geo &g = A.geo;
     const uint32_t todo = uniform_u32(A.unit_edges[slot]);
     if (todo == 0) return;
-    const UnitSetup u = unit_setup(A, unit, lane);
+    const UnitSetup u = unit_setup<FULL>(A, unit, lane);
     const uint32_t myqi = u.valid ? g.idx[u.v] : 0u;
     const_words_t cw = (const_words_t)(A.bits + uniform_u64(unit) * BITW);
     if (!SBITS)

@@ -71,15 +71,14 @@ struct Geo {
     const double2 *hsc;  // (sin(theta/2), cos(theta/2))
     const float4 *f32;   // (exp(r), exp(-r), sinh r, 0) rounded to FP32 (FP32 filter only)
     const uint32_t *btab;
-    // Update mode (re-query after a move), else null: nonzero for the points
-    // that moved, in sorted order.  Only moved points query, in every slab
-    // and in both directions, and a pair of two moved points is taken by the
-    // one that comes first in sorted order.
-    const uint8_t *moved;
-    // ~0, or 0 in update mode: a query's first slab with windows is its own
-    // slab & slab_mask (slab 0 in update mode), without a branch
-    uint32_t slab_mask;
+    // Update mode (re-query after a move), else null: bit s % 32 of word
+    // s / 32 is set for the points that moved, in sorted order.  Only moved
+    // points query, in every slab and in both directions, and a pair of two
+    // moved points is taken by the one that comes first in sorted order.
+    const uint32_t *moved;
 };
+
+__device__ __forceinline__ bool bit_of(const uint32_t *bits, uint32_t s) { return (bits[s >> 5] >> (s & 31u)) & 1u; }
 
 __device__ __forceinline__ uint32_t qang(double x) {
     // min(floor(x 2^27 / fl(2 pi)), 2^27 - 1), 0 below 0 (and for NaN); clamped

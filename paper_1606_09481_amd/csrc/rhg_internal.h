@@ -17,7 +17,7 @@ enum Slot {
     S_TH, S_EP, S_EM, S_SH, S_HS, S_HC, S_EP32, S_EM32, S_SH32,
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
-    S_SHARD, S_UDESC, S_MOVED, S_KEEPC, S_KEEPO, S_KEEPERR, S_SCANSCR3,
+    S_SHARD, S_UDESC, S_MOVED, S_MOVEDO, S_KEEPC, S_KEEPO, S_KEEPERR, S_SCANSCR3,
     S_COUNT
 };
 
@@ -85,7 +85,7 @@ struct Plan {
     // graph update: the old pairs kept (m_keep, written first, by the tile
     // offsets keep_off), then the m - m_keep pairs at moved points
     const int2 *old_pairs = nullptr;
-    const uint8_t *moved_orig = nullptr;
+    const uint32_t *moved_orig = nullptr;  // moved flags as bits, original order
     uint64_t m_old = 0, m_keep = 0;
     const uint64_t *keep_off = nullptr;
     uint32_t *keep_err = nullptr;

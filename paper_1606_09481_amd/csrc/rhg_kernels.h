@@ -56,15 +56,17 @@ void plan_scans(const uint64_t *cand, uint64_t nb, uint64_t *boff, uint64_t *nun
 // Dynamic model: one movement step of n nodes in place (S = sinh^2(alpha R / 2)).
 void move(uint64_t n, double alpha, double R, double S, double *theta, double *r, const double *tau_phi,
           double *tau_r, hipStream_t st);
-// Graph update after a move: out[s] = moved[idx[s]] != 0 (sorted order);
-// the old pairs whose ends both stayed, counted per tile of the list
-// (keep_tiles(m) tiles; *err set for an end outside 0..n-1) and written in
-// their order at out[offs[tile] ..].
-void moved_sorted(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint8_t *out, hipStream_t st);
+// Graph update after a move: bit s of out = moved[idx[s]] != 0 (sorted
+// order; idx null: moved[s], original order), moved_bit_words(n) words; the
+// old pairs whose ends both stayed (bits in original order), counted per tile
+// of the list (keep_tiles(m) tiles; *err set for an end outside 0..n-1) and
+// written in their order at out[offs[tile] ..].
+uint64_t moved_bit_words(uint64_t n);
+void moved_bits(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint32_t *out, hipStream_t st);
 uint64_t keep_tiles(uint64_t m);
-void keep_count(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,
+void keep_count(const int2 *pairs, uint64_t m, const uint32_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,
                 hipStream_t st);
-void keep_write(const int2 *pairs, uint64_t m, const uint8_t *moved, uint64_t n, const uint64_t *offs, int2 *out,
+void keep_write(const int2 *pairs, uint64_t m, const uint32_t *moved, uint64_t n, const uint64_t *offs, int2 *out,
                 uint32_t *err, hipStream_t st);
 // Query share k of S: out = {b0, b1, u0, u1, c0, c1}, the batch range [b0, b1)
 // cut where the candidate prefix boff crosses k/S and (k+1)/S of the total,

@@ -311,7 +311,6 @@ static float round_up_f32(double x) {
 // the FP32 filter thresholds.
 void geo_static(const Plan &pl, Geo &g) {
     std::memset(&g, 0, sizeof(Geo));
-    g.slab_mask = ~0u;
     g.n = (uint32_t)pl.n;
     g.B = pl.B;
     g.R = pl.R;
@@ -387,12 +386,14 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     }
     rhgk::gather(src, vals, n, th, epm, sh, hsc, f32, st);
     const bool update = rq.moved != nullptr;
-    uint8_t *msorted = nullptr;
+    uint32_t *msorted = nullptr, *morig = nullptr;
     if (update) {
         if (S > 1) return RHG_EINVAL;  // an update is one whole graph
-        msorted = (uint8_t *)c->buf(S_MOVED, n);
-        if (!msorted) return RHG_ENOMEM;
-        rhgk::moved_sorted(vals, rq.moved, n, msorted, st);
+        msorted = (uint32_t *)c->buf(S_MOVED, sizeof(uint32_t) * rhgk::moved_bit_words(n));
+        morig = (uint32_t *)c->buf(S_MOVEDO, sizeof(uint32_t) * rhgk::moved_bit_words(n));
+        if (!msorted || !morig) return RHG_ENOMEM;
+        rhgk::moved_bits(vals, rq.moved, n, msorted, st);
+        rhgk::moved_bits(nullptr, rq.moved, n, morig, st);
     }
     RHG_HIP(hipEventRecord(c->ev[EV_TABLE1], st));
 
@@ -436,7 +437,6 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.f32 = f32;
     g.btab = btab;
     g.moved = msorted;
-    g.slab_mask = update ? 0u : ~0u;
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     rhgk::bucket_index(g, btab, st);
 
@@ -542,12 +542,12 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
         void *scan3 = c->buf(S_SCANSCR3, rhgk::scan_scratch_bytes(tiles));
         if (!scan3) return RHG_ENOMEM;
         RHG_HIP(hipMemsetAsync(kerr, 0, sizeof(uint32_t), st));
-        rhgk::keep_count((const int2 *)rq.old_pairs, rq.m_old, rq.moved, n, kcnt, kerr, st);
+        rhgk::keep_count((const int2 *)rq.old_pairs, rq.m_old, morig, n, kcnt, kerr, st);
         rhgk::scan_u32(kcnt, koff, tiles, scan3, st);
         RHG_HIP(hipMemcpyAsync(pin + 6, koff + tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
         RHG_HIP(hipMemcpyAsync(keep_err_host, kerr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         pl.old_pairs = (const int2 *)rq.old_pairs;
-        pl.moved_orig = rq.moved;
+        pl.moved_orig = morig;
         pl.m_old = rq.m_old;
         pl.keep_off = koff;
         pl.keep_err = kerr;
