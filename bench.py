@@ -464,8 +464,8 @@ def main():
                 "traffic_frac": (traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None}
 
     # the dominant kernel is the longer of the two query kernels of the timed FP64 step
-    r_emit = roofline("k_emit<false>", "k_emit", emit_b, ph["emit"])
-    r_count = roofline("k_count<0,false>", "k_count", cnt_b, f64["count_kernel_ms"])
+    r_emit = roofline("k_emit<false,false>", "k_emit", emit_b, ph["emit"])
+    r_count = roofline("k_count<0,false,false>", "k_count", cnt_b, f64["count_kernel_ms"])
     roof, other = (r_emit, r_count) if ph["emit"] >= f64["count_kernel_ms"] else (r_count, r_emit)
     roof = dict(roof, other=other)
     line = {
