@@ -484,6 +484,26 @@ struct CountSmem {
     uint32_t qpos[FULL ? 64 : 1];  // per rank: the query's sorted position (update mode)
 };
 
+// Ranks and positions of one count step (VT x 64 candidates from t0): the
+// rank of each candidate's window and its position in the slab; lanes at or
+// past the segment end e take the dummy position bs.  Advances base.
+template <int VT>
+__device__ __forceinline__ void count_positions(uint8_t *flags, const uint32_t *pbs, int lane, bool ne, uint32_t relu,
+                                                uint32_t t0, uint32_t e, uint32_t bs, uint32_t be, uint32_t nj,
+                                                uint32_t &base, uint32_t (&p)[VT], uint32_t (&rk)[VT]) {
+    uint64_t M[VT];
+    uint32_t upto[VT];
+    step_starts<VT>(flags, lane, ne, relu, t0, M, upto);
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        const uint32_t t = t0 + 64u * i + lane;
+        rk[i] = (base - 1u + upto[i]) & 63u;
+        base += (uint32_t)__popcll(M[i]);
+        const uint32_t pp = position_pb(pbs[rk[i]], t, be, nj);
+        p[i] = t < e ? pp : bs;
+    }
+}
+
 // FULL: update mode (Geo::moved): a candidate that passes the distance test
 // is an edge unless it is the query itself, or a moved point that comes
 // before the query in sorted order (that pair is the other query's).
@@ -545,28 +565,19 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         }
         uint32_t base = (uint32_t)__popcll(__ballot(ne && relu == BEFORE_UNIT));
         const uint32_t bs = g.bs[j], be = g.bs[j + 1], nj = be - bs;
+        // The ranks and positions of step k+1 (LDS only) are worked out while
+        // the gathers of step k are in flight, off the step's chain of waits.
+        uint32_t p[VT], rk[VT];
+        count_positions<VT>(S.flag, S.pb, lane, ne, relu, 0u, e, bs, be, nj, base, p, rk);
         for (uint32_t t0 = 0; t0 < e; t0 += 64u * VT) {
-            uint64_t M[VT];
-            uint32_t upto[VT];
-            step_starts<VT>(S.flag, lane, ne, relu, t0, M, upto);
-            // Lanes past the segment's end take a dummy candidate (position bs,
-            // rank masked into range) whose result is dropped.
-            uint32_t p[VT], rk[VT];
-            bool act[VT];
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const uint32_t t = t0 + 64u * i + lane;
-                act[i] = t < e;
-                rk[i] = (base - 1u + upto[i]) & 63u;
-                base += (uint32_t)__popcll(M[i]);
-                const uint32_t pp = position_pb(S.pb[rk[i]], t, be, nj);
-                p[i] = act[i] ? pp : bs;
-            }
             Cand c[VT];
 #pragma unroll
             for (int i = 0; i < VT; ++i) load_cand<FP32, WIDE>(g, p[i], c[i]);
+            uint32_t pn[VT] = {}, rkn[VT] = {};
+            if (t0 + 64u * VT < e) count_positions<VT>(S.flag, S.pb, lane, ne, relu, t0 + 64u * VT, e, bs, be, nj, base, pn, rkn);
 #pragma unroll
             for (int i = 0; i < VT; ++i) {
+                const bool act = t0 + 64u * i + lane < e;
                 Qv q;
                 q.hep = S.qd[0][rk[i]];
                 q.hem = S.qd[1][rk[i]];
@@ -580,8 +591,8 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 }
                 // FP32 filter: test every lane and mask (the loads issue together);
                 // FP64: lanes past the end skip the test (measured faster there)
-                const uint32_t r = FP32 ? (edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) & (act[i] ? 7u : 0u))
-                                        : (act[i] ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
+                const uint32_t r = FP32 ? (edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) & (act ? 7u : 0u))
+                                        : (act ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
                 int flag = (int)(r & 1u);
                 if (FULL) {
                     const uint32_t qp = S.qpos[rk[i]];
@@ -596,6 +607,11 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 if (t0 + 64u * i < e && lane == 0) S.bits[word + i] = m;
             }
             word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
+#pragma unroll
+            for (int i = 0; i < VT; ++i) {
+                p[i] = pn[i];
+                rk[i] = rkn[i];
+            }
         }
     }
     wave_lds_sync();
