@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(n, windows, units, m):
-    """Algorithmic HBM bytes per launch of the two query kernels (see DESIGN.md):
+    """Algorithmic HBM bytes per launch of the two query kernels:
     count reads the 5 FP64 table columns once per point (40 B), each window
     record (8 B) and writes one count per unit (4 B); emit reads the same plus
     the original index (4 B per point) and writes one int32 pair per edge (8 B)."""
