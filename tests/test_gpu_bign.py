@@ -57,3 +57,53 @@ def test_big_n_table_mode(orc, n, alpha, kbar, precs):
             assert len(got) == len(ref) and np.array_equal(got, ref), "precision %d" % prec
     finally:
         rhg.rhg_ctx_destroy(c)
+
+
+def _sorted_keys(g):
+    """Sorted canonical keys lo * 2^32 + hi of a graph's edges, on the device."""
+    import torch
+    m = rhg.rhg_graph_num_edges(g)
+    e = _device_view(rhg.rhg_graph_edges_device(g), 2 * m).view(-1, 2).long()
+    assert bool((e[:, 0] < e[:, 1]).all()), "lo < hi"
+    return torch.sort((e[:, 0] << 32) | e[:, 1]).values
+
+
+def test_big_n_update_after_move():
+    """n = 2^28 + 3 (64-bit table offsets) in update mode: the graph after a
+    move of 12% of the nodes, updated from the graph before it, has exactly
+    the edge set of its regeneration (sorted and compared on the device)."""
+    import torch
+    n, alpha, kbar = (1 << 28) + 3, 1.0, 4.0
+    print("case update", n, alpha, kbar, flush=True)
+    rhg.load()
+    torch.cuda.set_device(0)
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    try:
+        R = rhg.rhg_target_radius(n, alpha, kbar)
+        gen = torch.Generator(device="cuda").manual_seed(11)
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+        th = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * (2 * math.pi)
+        r = (2.0 * torch.asinh(torch.sqrt(u) * math.sinh(alpha * R / 2.0)) / alpha).clamp_(max=R)  # Eq. 1
+        del u
+        g0 = rhg.rhg_generate_from_coords(c, th, r, R)
+        m0 = rhg.rhg_graph_num_edges(g0)
+        sel = torch.rand(n, device="cuda", generator=gen) < 0.12
+        tp = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1, 0.0)
+        tr = torch.where(sel, torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * 11 - 10, 0.0)
+        rhg.rhg_move(c, th, r, tp, tr, alpha, R)
+        del tp, tr
+        moved = sel.to(torch.uint8)
+        torch.cuda.synchronize()
+        gu = rhg.rhg_update_after_move(c, th, r, R, moved, rhg.rhg_graph_edges_device(g0), m0)
+        rhg.rhg_graph_free(g0)
+        ku = _sorted_keys(gu)
+        rhg.rhg_graph_free(gu)
+        gr = rhg.rhg_generate_from_coords(c, th, r, R)
+        kr = _sorted_keys(gr)
+        rhg.rhg_graph_free(gr)
+        print("edges before %d, after %d" % (m0, len(kr)), flush=True)
+        assert len(ku) == len(kr) and bool(torch.equal(ku, kr))
+        assert bool((ku[1:] != ku[:-1]).all()), "each edge once"
+    finally:
+        rhg.rhg_ctx_destroy(c)
+        torch.cuda.empty_cache()
