@@ -129,8 +129,7 @@ __device__ __forceinline__ void point_table(const Source &s, uint64_t i, double 
         ep = exp(r);
         em = exp(-r);
         sh = sinh(r);
-        hs = sin(theta * 0.5);
-        hc = cos(theta * 0.5);
+        sincos(theta * 0.5, &hs, &hc);  // one argument reduction for both
     }
 }
 
