@@ -122,3 +122,53 @@ def test_update_rejects_bad_pairs(ctx, orc):
     g = rhg.rhg_update_after_move(ctx, dth, dr, R, moved, 0, 0)  # no old edges, nothing moved: no edges
     assert rhg.rhg_graph_num_edges(g) == 0
     rhg.rhg_graph_free(g)
+
+
+@pytest.mark.parametrize("n", [2, 3, 64, 65, 129])
+def test_update_tiny_and_ragged(ctx, orc, n):
+    """One or two batches, a ragged last batch: every case of half and all moved."""
+    kbar = min(1.5, (n - 1) / 2.0)
+    for frac, seed in ((0.5, 20 + n), (1.0, 40 + n)):
+        _update_case(ctx, orc, n, 1.0, kbar, frac, seed)
+
+
+def test_update_from_empty_old_list(ctx, orc):
+    """No old edges and every point flagged: the update is a whole generation."""
+    import torch
+    n = 5_000
+    R = orc.target_radius(n, 1.0, 10.0)
+    th, r = orc.sample(n, 1.0, R, 31)
+    dth, dr = _dev(th), _dev(r)
+    moved = torch.ones(n, dtype=torch.uint8, device="cuda")
+    g = rhg.rhg_update_after_move(ctx, dth, dr, R, moved, 0, 0)
+    e = rhg.rhg_graph_copy_edges(g)
+    rhg.rhg_graph_free(g)
+    g2 = rhg.rhg_generate_from_coords(ctx, dth, dr, R)
+    e2 = rhg.rhg_graph_copy_edges(g2)
+    rhg.rhg_graph_free(g2)
+    parity.assert_valid(e, n)
+    parity.assert_same(e, e2)
+
+
+def test_update_fp32_exhaustive_no_disagreement(ctx, orc):
+    """The FP32 filter's self-check in update mode: no pair decided by the
+    filter differs from the FP64 test."""
+    rhg.rhg_ctx_set_option(ctx, rhg.RHG_OPT_FP32_EXHAUSTIVE, 1)
+    try:
+        n, alpha, kbar = 30_000, 0.8, 20.0
+        R = orc.target_radius(n, alpha, kbar)
+        import torch
+        dth, dr, dth1, dr1, dtp, dtr, who = _moved_state(orc, n, alpha, R, 0.2, 50)
+        g0 = rhg.rhg_generate_from_coords(ctx, dth, dr, R)
+        m0 = rhg.rhg_graph_num_edges(g0)
+        rhg.rhg_move(ctx, dth1, dr1, dtp, dtr, alpha, R)
+        moved = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        moved[_dev(who.astype(np.int64))] = 1
+        g1 = rhg.rhg_update_after_move(ctx, dth1, dr1, R, moved, rhg.rhg_graph_edges_device(g0), m0,
+                                       rhg.RHG_FP32_RECHECK)
+        st = rhg.rhg_graph_stats(g1)
+        rhg.rhg_graph_free(g1)
+        rhg.rhg_graph_free(g0)
+        assert st["disagreements"] == 0 and st["candidates"] > 0
+    finally:
+        rhg.rhg_ctx_set_option(ctx, rhg.RHG_OPT_FP32_EXHAUSTIVE, 0)
