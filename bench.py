@@ -152,6 +152,44 @@ def run_shares(args):
             "max_ms": max(x["ms"] for x in per), "mean_ms": sum(x["ms"] for x in per) / S, "shares": per}
 
 
+def run_csr(args):
+    """Symmetric CSR adjacency (rhg_csr_from_pairs) of the benchmark graph: the
+    FP64 edge list emitted into a device tensor, then rows and columns built
+    on the device (host-timed, synchronous call; 1 warm-up + 3 timed)."""
+    import torch
+    from paper_1606_09481_amd import rhg
+
+    rhg.load()
+    torch.cuda.set_device(0)
+    ctx = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    try:
+        p = rhg.params(args.n, args.alpha, kbar=args.kbar, seed=args.seed, precision=rhg.RHG_FP64)
+        plan, m = rhg.rhg_count(ctx, p)
+        pairs = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+        rhg.rhg_emit(ctx, plan, pairs, m)
+        rhg.rhg_graph_free(plan)
+        row_ptr = torch.empty(args.n + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+        ts = []
+        for it in range(1 + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rhg.rhg_csr_from_pairs(ctx, args.n, pairs, m, row_ptr, col)
+            t1 = time.perf_counter()
+            if it >= 1:
+                ts.append(t1 - t0)
+        t = sum(ts) / len(ts)
+        deg = row_ptr[1:] - row_ptr[:-1]
+        res = {"ms": 1e3 * t, "edges": m, "entries": 2 * m, "entries_per_s": 2 * m / t,
+               "max_degree": int(deg.max().item()), "isolated": int((deg == 0).sum().item()),
+               "what": "rhg_csr_from_pairs: 2 directed entries per edge, stable radix sort by row, row pointers"}
+        del pairs, row_ptr, col, deg
+    finally:
+        rhg.rhg_ctx_destroy(ctx)
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_dynamic(args):
     """Dynamic model (Sec. III-C) at the benchmark size: one movement step of
     all nodes and of 12% of them (tau_phi in (-1, 1), tau_r in (-10, 1), the
@@ -431,6 +469,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-model timing")
+    ap.add_argument("--no-csr", action="store_true", help="skip the CSR adjacency timing")
     ap.add_argument("--shares", type=int, default=8,
                     help="also time each of this many one-GPU query shares (0: skip)")
     args = ap.parse_args()
@@ -492,6 +531,8 @@ def main():
         line["share"] = run_shares(args)
     if not args.no_dynamic:
         line["dynamic"] = run_dynamic(args)
+    if not args.no_csr:
+        line["csr"] = run_csr(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args, f64["m"])
     print(json.dumps(line), flush=True)

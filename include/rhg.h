@@ -230,6 +230,22 @@ rhg_status rhg_update_after_move(rhg_ctx *ctx, uint64_t n, const double *theta, 
                                  rhg_precision precision, const uint8_t *moved, const int32_t *old_pairs,
                                  uint64_t m_old, rhg_graph **out);
 
+/* Symmetric CSR adjacency of an edge list (the graph-construction step after
+ * generation): row v of the n rows holds every w with (v, w) or (w, v) among
+ * the pairs.
+ *   pairs    device int32 (lo, hi) pairs, m of them, ends in 0..n-1 (e.g.
+ *            rhg_graph_edges_device or an rhg_emit tensor); read only.
+ *   row_ptr  device uint64[n + 1]: row v is col[row_ptr[v] .. row_ptr[v+1]).
+ *   col      device int32[2m].
+ * Each pair becomes two directed entries, ordered by a stable sort by row, so
+ * within a row the neighbours keep the order of their pairs in the list and
+ * the result is deterministic.  Work buffers of about 14 bytes per entry
+ * belong to the context.  Synchronous on the context stream.  RHG_EINVAL:
+ * null context, n < 1, null arrays, an end outside 0..n-1 (nothing written);
+ * RHG_ERANGE: n >= 2^31 or m >= 2^31. */
+rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t *pairs, uint64_t m, uint64_t *row_ptr,
+                              int32_t *col);
+
 /* Two-phase form for caller-owned output (e.g. a PyTorch tensor):
  * rhg_count plans and counts (m), rhg_emit writes the m pairs into
  * dev_pairs (device, >= 2*m int32, capacity_pairs in pairs; RHG_ETRUNC if

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librhg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["keys_sort.hip", "scan.hip", "query.hip", "small.hip", "dynamic.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["keys_sort.hip", "scan.hip", "query.hip", "small.hip", "dynamic.hip", "csr.hip", "runtime.cpp", "server.cpp"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",

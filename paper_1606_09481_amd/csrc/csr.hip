@@ -1,0 +1,52 @@
+// csr.hip -- symmetric CSR adjacency of an edge list: row v holds every w
+// with (v, w) or (w, v) in the list.  Each pair becomes two directed entries
+// (row, neighbour); a stable LSD radix sort by row (the sort of the slab
+// keys) orders them, so within a row the neighbours keep the order of the
+// pairs in the list; the row pointers are the first entry of each row in the
+// sorted rows.
+#include "rhg_kernels.h"
+
+namespace rhgk {
+using namespace rhgd;
+
+// Entries 2e and 2e + 1 of pair e: (lo, hi) and (hi, lo).  An end outside
+// 0..n-1 raises *err (the caller stops before sorting) and is written as 0,
+// so no later step indexes outside row_ptr.
+__global__ __launch_bounds__(256) void k_directed(const int2 *pairs, uint64_t m, uint32_t n, uint2 *rows,
+                                                  uint2 *nbrs, uint32_t *err) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int2 p = pairs[e];
+    uint32_t a = (uint32_t)p.x, b = (uint32_t)p.y;
+    if (a >= n || b >= n) {
+        atomicOr(err, 1u);
+        a = b = 0u;
+    }
+    rows[e] = make_uint2(a, b);
+    nbrs[e] = make_uint2(b, a);
+}
+
+void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err,
+              hipStream_t st) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_directed, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pairs, m, (uint32_t)n,
+                       (uint2 *)rows, (uint2 *)nbrs, err);
+}
+
+// row_ptr[v] = first sorted entry with row >= v, v = 0..n: entry i writes the
+// rows in (row[i-1], row[i]] (with row[-1] = -1 and row[len] = n), so every
+// row pointer is written once, the empty rows by the entry after them.
+__global__ __launch_bounds__(256) void k_row_ptr(const uint32_t *rows, uint64_t len, uint32_t n, uint64_t *row_ptr) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > len) return;
+    const int64_t prev = i ? (int64_t)rows[i - 1] : -1;
+    const int64_t cur = i < len ? (int64_t)rows[i] : (int64_t)n;
+    for (int64_t v = prev + 1; v <= cur; ++v) row_ptr[v] = i;
+}
+
+void row_pointers(const uint32_t *rows, uint64_t len, uint64_t n, uint64_t *row_ptr, hipStream_t st) {
+    hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)((len + 1 + 255) / 256)), dim3(256), 0, st, rows, len, (uint32_t)n,
+                       row_ptr);
+}
+
+}  // namespace rhgk

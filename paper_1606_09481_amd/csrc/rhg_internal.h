@@ -18,6 +18,7 @@ enum Slot {
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
     S_SHARD, S_UDESC, S_MOVED, S_MOVEDO, S_KEEPC, S_KEEPO, S_KEEPERR, S_SCANSCR3,
+    S_CSRROWS, S_CSRROWS2, S_CSRNBRS2, S_CSRSCR, S_CSRERR,
     S_COUNT
 };
 

@@ -62,6 +62,12 @@ void move(uint64_t n, double alpha, double R, double S, double *theta, double *r
 // of the list (keep_tiles(m) tiles; *err set for an end outside 0..n-1) and
 // written in their order at out[offs[tile] ..].
 uint64_t moved_bit_words(uint64_t n);
+// CSR: the 2m directed entries of m pairs (rows[2e..2e+1] = lo, hi; nbrs the
+// other ends; *err set for an end outside 0..n-1, written as 0), and the row
+// pointers row_ptr[0..n] of rows sorted by row (len entries, rows < n).
+void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err,
+              hipStream_t st);
+void row_pointers(const uint32_t *rows, uint64_t len, uint64_t n, uint64_t *row_ptr, hipStream_t st);
 void moved_bits(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint32_t *out, hipStream_t st);
 uint64_t keep_tiles(uint64_t m);
 void keep_count(const int2 *pairs, uint64_t m, const uint32_t *moved, uint64_t n, uint32_t *counts, uint32_t *err,

@@ -779,6 +779,40 @@ extern "C" rhg_status rhg_update_after_move(rhg_ctx *ctx, uint64_t n, const doub
     return s;
 }
 
+extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t *pairs, uint64_t m,
+                                         uint64_t *row_ptr, int32_t *col) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || n < 1 || !row_ptr || (m && (!pairs || !col))) return RHG_EINVAL;
+    if (n >= N_MAX || m >= (1ull << 31)) return RHG_ERANGE;  // rows and entries indexed in 32 bits
+    RHG_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();
+    const hipStream_t st = c->stream;
+    const uint64_t len = 2 * m;
+    uint32_t *rows = nullptr;
+    if (len) {
+        rows = (uint32_t *)c->buf(S_CSRROWS, sizeof(uint32_t) * len);
+        uint32_t *rows2 = (uint32_t *)c->buf(S_CSRROWS2, sizeof(uint32_t) * len);
+        uint32_t *nbrs2 = (uint32_t *)c->buf(S_CSRNBRS2, sizeof(uint32_t) * len);
+        uint32_t *err = (uint32_t *)c->buf(S_CSRERR, sizeof(uint32_t));
+        void *scr = c->buf(S_CSRSCR, rhgk::sort_scratch_bytes(len));
+        if (!rows || !rows2 || !nbrs2 || !err || !scr) return RHG_ENOMEM;
+        RHG_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), st));
+        rhgk::directed((const int2 *)pairs, m, n, rows, (uint32_t *)col, err, st);
+        uint32_t *err_host = (uint32_t *)((char *)c->pinned + 1036);
+        RHG_HIP(hipMemcpyAsync(err_host, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        RHG_HIP(hipStreamSynchronize(st));
+        if (*err_host != 0) return RHG_EINVAL;  // an end outside 0..n-1: nothing sorted or written
+        // stable by row: a row's neighbours keep the order of their pairs
+        rhgk::radix_sort(rows, (uint32_t *)col, rows2, nbrs2, scr, len, std::max(1, ceil_log2(n)), st);
+        RHG_HIP(hipMemcpyAsync(err_host, rhgk::sort_error_flag(scr), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    }
+    rhgk::row_pointers(rows, len, n, row_ptr, st);
+    RHG_HIP(hipStreamSynchronize(st));
+    RHG_HIP(hipGetLastError());
+    if (len && *(uint32_t *)((char *)c->pinned + 1036) != 0) return RHG_EDEVICE;  // a sort pass gave up waiting
+    return RHG_OK;
+}
+
 extern "C" rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,
                                const double *tau_phi, double *tau_r) {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);

@@ -98,6 +98,7 @@ def load(path: Optional[str] = None):
         "rhg_generate_from_table": (i32, [vp, u64, vp, vp, vp, d, i32, i32, P(vp)]),
         "rhg_move": (i32, [vp, u64, d, d, vp, vp, vp, vp]),
         "rhg_update_after_move": (i32, [vp, u64, vp, vp, d, i32, vp, vp, u64, P(vp)]),
+        "rhg_csr_from_pairs": (i32, [vp, u64, vp, u64, vp, vp]),
         "rhg_count": (i32, [vp, P(rhg_params), P(vp), P(u64)]),
         "rhg_emit": (i32, [vp, vp, vp, u64]),
         "rhg_graph_num_edges": (i32, [vp, P(u64)]),
@@ -259,6 +260,15 @@ def rhg_update_after_move(ctx, theta, r, R: float, moved, old_pairs, m_old: int,
     _check(load().rhg_update_after_move(ctx, n, _ptr(theta), _ptr(r), float(R), int(precision), _ptr(moved),
                                         _ptr(old_pairs), int(m_old), ctypes.byref(g)), "rhg_update_after_move")
     return g
+
+
+def rhg_csr_from_pairs(ctx, n: int, pairs, m: int, row_ptr, col):
+    """Symmetric CSR of m device pairs: row_ptr (uint64/int64 tensor, n + 1)
+    and col (int32 tensor, 2m) on the GPU; pairs a device tensor or address."""
+    if int(row_ptr.numel()) < int(n) + 1 or (int(m) and int(col.numel()) < 2 * int(m)):
+        raise ValueError("rhg_csr_from_pairs: output arrays too small")
+    _check(load().rhg_csr_from_pairs(ctx, int(n), _ptr(pairs), int(m), _ptr(row_ptr), _ptr(col)),
+           "rhg_csr_from_pairs")
 
 
 def rhg_count(ctx, p: rhg_params) -> Tuple[ctypes.c_void_p, int]:

@@ -78,6 +78,7 @@ def test_null_handles_rejected(lib):
     assert lib.rhg_move(None, 10, 1.0, 5.0, None, None, None, None) == rhg.RHG_EINVAL
     assert lib.rhg_move(None, 0, 1.0, 5.0, None, None, None, None) == rhg.RHG_EINVAL  # null context first
     assert lib.rhg_update_after_move(None, 10, None, None, 5.0, 0, None, None, 0, ctypes.byref(g)) == rhg.RHG_EINVAL
+    assert lib.rhg_csr_from_pairs(None, 10, None, 0, None, None) == rhg.RHG_EINVAL
     assert lib.rhg_graph_stats(None, None) == rhg.RHG_EINVAL
     lib.rhg_graph_free(None)
     lib.rhg_ctx_destroy(None)

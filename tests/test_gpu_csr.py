@@ -1,0 +1,107 @@
+"""GPU parity of the symmetric CSR adjacency (rhg_csr_from_pairs): row v
+holds every w with (v, w) or (w, v) in the edge list.
+
+The rows of the device CSR, as sets, must equal those built on the host from
+the oracle's edge set (band sweep on the table the device used); the row
+pointers must count each vertex's degree, isolated vertices included; within
+a row the neighbours keep the order of their pairs in the input list (the
+sort by row is stable).  Also: an empty list, a pair naming point n, n = 10^6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1606_09481_amd import rhg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    rhg.load()
+    torch.cuda.set_device(0)
+    c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    yield c
+    rhg.rhg_ctx_destroy(c)
+
+
+def _csr(ctx, n, pairs_dev, m):
+    import torch
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(2 * m, 1), dtype=torch.int32, device="cuda")
+    rhg.rhg_csr_from_pairs(ctx, n, pairs_dev, m, row_ptr, col)
+    torch.cuda.synchronize()
+    return row_ptr.cpu().numpy(), col[:2 * m].cpu().numpy()
+
+
+def _host_rows(e, n):
+    """Rows of the symmetric adjacency of pairs e, neighbours in pair order."""
+    src = np.concatenate([e[:, 0], e[:, 1]]).astype(np.int64)
+    dst = np.concatenate([e[:, 1], e[:, 0]]).astype(np.int64)
+    pos = np.concatenate([2 * np.arange(len(e)), 2 * np.arange(len(e)) + 1])
+    order = np.lexsort((pos, src))
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, src + 1, 1)
+    return np.cumsum(ptr), dst[order]
+
+
+def _rows_as_sets_equal(ptr_a, col_a, ptr_b, col_b):
+    assert np.array_equal(ptr_a, ptr_b), "row pointers (degrees) differ"
+    n = len(ptr_a) - 1
+    # sort within rows: key row * 2^32 + neighbour
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(ptr_a))
+    ka = np.sort(rows * (1 << 32) + col_a.astype(np.int64))
+    kb = np.sort(rows * (1 << 32) + col_b.astype(np.int64))
+    assert np.array_equal(ka, kb), "row contents differ"
+
+
+@pytest.mark.parametrize("n,alpha,kbar,seed", [(20_000, 1.0, 10.0, 1), (30_001, 0.55, 6.0, 2), (5_000, 1.5, 2.0, 3)])
+def test_csr_matches_oracle_rows(ctx, orc, n, alpha, kbar, seed):
+    import torch
+    print("case", n, alpha, kbar, seed, flush=True)
+    R = orc.target_radius(n, alpha, kbar)
+    th, r = orc.sample(n, alpha, R, seed)
+    t = orc.table(th, r)
+    g = rhg.rhg_generate_from_table(ctx, th, r, t, R)
+    m = rhg.rhg_graph_num_edges(g)
+    ptr, col = _csr(ctx, n, rhg.rhg_graph_edges_device(g), m)
+    e_gpu = rhg.rhg_graph_copy_edges(g)
+    rhg.rhg_graph_free(g)
+    ref = orc.band_sweep(th, r, t, R, math.cosh(R))
+    rptr, rcol = _host_rows(np.asarray(ref).reshape(-1, 2), n)
+    _rows_as_sets_equal(ptr, col, rptr, rcol)
+    # stable: within a row, the order of the pairs in the device list
+    sptr, scol = _host_rows(e_gpu, n)
+    assert np.array_equal(ptr, sptr) and np.array_equal(col, scol)
+    assert (np.diff(ptr) == 0).sum() > 0 or kbar > 5  # sparse case has isolated vertices
+
+
+def test_csr_1e6_degrees_and_rows(ctx):
+    """n = 10^6, kbar = 20: the device CSR of the device edge list equals the
+    host's stable transpose-closure of the same list."""
+    import torch
+    n = 1_000_000
+    p = rhg.params(n, 1.0, kbar=20, seed=4)
+    plan, m = rhg.rhg_count(ctx, p)
+    out = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+    rhg.rhg_emit(ctx, plan, out, m)
+    rhg.rhg_graph_free(plan)
+    ptr, col = _csr(ctx, n, out, m)
+    e = out.view(-1, 2).cpu().numpy()
+    hptr, hcol = _host_rows(e, n)
+    assert np.array_equal(ptr, hptr) and np.array_equal(col, hcol)
+
+
+def test_csr_empty_and_rejects(ctx):
+    import torch
+    ptr, col = _csr(ctx, 1000, 0, 0)
+    assert np.all(ptr == 0)
+    bad = torch.tensor([0, 1, 2, 1000], dtype=torch.int32, device="cuda")
+    row_ptr = torch.zeros(1001, dtype=torch.int64, device="cuda")
+    colb = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(rhg.RhgError) as ei:
+        rhg.rhg_csr_from_pairs(ctx, 1000, bad, 2, row_ptr, colb)
+    assert ei.value.status == rhg.RHG_EINVAL
+    assert int(row_ptr.abs().sum()) == 0  # nothing written
