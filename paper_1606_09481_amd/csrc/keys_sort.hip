@@ -309,8 +309,10 @@ size_t sort_scratch_bytes(uint64_t n) {
            (uint64_t)S_MAX_PASSES * (ntiles ? ntiles : 1) * 256 * sizeof(uint64_t);
 }
 
+int sort_passes(int bits) { return std::min((bits + 7) / 8, S_MAX_PASSES); }
+
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
-                int bits, hipStream_t st) {
+                int bits, hipStream_t st, bool copy_back) {
     if (n < 2) return;
     const uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
     int passes = (bits + 7) / 8;
@@ -329,7 +331,7 @@ void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *va
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    if (ka != keys) {
+    if (ka != keys && copy_back) {
         (void)hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     }

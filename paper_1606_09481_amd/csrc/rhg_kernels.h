@@ -18,14 +18,17 @@ void keys(const rhgd::Source &src, int B, const double *c_host, uint32_t *keys, 
 void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStream_t st);
 
 // a3: stable LSD radix sort of (keys, vals), `bits` low key bits, 8 per pass;
-// the result ends in (keys, vals); tmp buffers of n each; scratch from
-// sort_scratch_bytes.
+// the result ends in (keys, vals) (copied back after an odd number of
+// passes); tmp buffers of n each; scratch from sort_scratch_bytes.
+// sort_passes(bits) passes: with an odd count a caller that wants no copy
+// back passes its buffers the other way round.
 // Device flag (u32) a sort raises if a look-back made no progress for its
 // whole spin budget (never expected; the sorted output is then invalid).
 uint32_t *sort_error_flag(void *scratch);
 size_t sort_scratch_bytes(uint64_t n);
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
-                int bits, hipStream_t st);
+                int bits, hipStream_t st, bool copy_back = true);
+int sort_passes(int bits);
 
 // a1 + a3 gather: per sorted position, the point's angle and table
 // (computed, or copied from the caller's table) in sorted order.
