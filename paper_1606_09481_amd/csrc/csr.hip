@@ -35,17 +35,38 @@ void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_
 
 // row_ptr[v] = first sorted entry with row >= v, v = 0..n: entry i writes the
 // rows in (row[i-1], row[i]] (with row[-1] = -1 and row[len] = n), so every
-// row pointer is written once, the empty rows by the entry after them.
+// row pointer is written once, the empty rows by the entry after them.  A
+// thread takes entries 4q .. 4q+3 (one 16-byte load where all four exist and
+// rows is 16-byte aligned).
 __global__ __launch_bounds__(256) void k_row_ptr(const uint32_t *rows, uint64_t len, uint32_t n, uint64_t *row_ptr) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > len) return;
-    const int64_t prev = i ? (int64_t)rows[i - 1] : -1;
-    const int64_t cur = i < len ? (int64_t)rows[i] : (int64_t)n;
-    for (int64_t v = prev + 1; v <= cur; ++v) row_ptr[v] = i;
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i0 = 4 * q;
+    if (i0 > len) return;
+    uint32_t k[4];
+    if (i0 + 4 <= len && ((uintptr_t)rows & 15u) == 0) {
+        const uint4 x = ((const uint4 *)rows)[q];
+        k[0] = x.x;
+        k[1] = x.y;
+        k[2] = x.z;
+        k[3] = x.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = i0 + j < len ? rows[i0 + j] : n;
+    }
+    int64_t prev = i0 ? (int64_t)rows[i0 - 1] : -1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t i = i0 + j;
+        if (i > len) break;
+        const int64_t cur = i < len ? (int64_t)k[j] : (int64_t)n;
+        for (int64_t v = prev + 1; v <= cur; ++v) row_ptr[v] = i;
+        prev = cur;
+    }
 }
 
 void row_pointers(const uint32_t *rows, uint64_t len, uint64_t n, uint64_t *row_ptr, hipStream_t st) {
-    hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)((len + 1 + 255) / 256)), dim3(256), 0, st, rows, len, (uint32_t)n,
+    const uint64_t threads = len / 4 + 1;
+    hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, rows, len, (uint32_t)n,
                        row_ptr);
 }
 
