@@ -141,10 +141,13 @@ static SortScratch sort_scratch(void *scratch, uint32_t ntiles) {
 
 __global__ __launch_bounds__(S_THREADS) void k_digit_counts(const uint32_t *keys, uint32_t n, int passes,
                                                             uint32_t *counts) {
-    __shared__ uint32_t h[4][S_MAX_PASSES][256];
-    const int w = threadIdx.x >> 6;
+    // 16 copies of the histograms, lane l counting into copy l mod 16: keys
+    // that repeat over long runs (the rows of a CSR's directed entries) then
+    // put at most 4 lanes of an LDS atomic on one address, not 64
+    __shared__ uint32_t h[16][S_MAX_PASSES][256];
+    const int w = threadIdx.x & 15;
     for (int q = 0; q < S_MAX_PASSES; ++q)
-        for (int x = 0; x < 4; ++x) h[x][q][threadIdx.x] = 0;
+        for (int x = 0; x < 16; ++x) h[x][q][threadIdx.x] = 0;
     __syncthreads();
     // 16-byte loads where the keys are 16-byte aligned (every buffer here is);
     // otherwise the scalar tail below takes all of them
@@ -165,7 +168,8 @@ __global__ __launch_bounds__(S_THREADS) void k_digit_counts(const uint32_t *keys
     }
     __syncthreads();
     for (int q = 0; q < passes; ++q) {
-        const uint32_t t = h[0][q][threadIdx.x] + h[1][q][threadIdx.x] + h[2][q][threadIdx.x] + h[3][q][threadIdx.x];
+        uint32_t t = 0;
+        for (int x = 0; x < 16; ++x) t += h[x][q][threadIdx.x];
         if (t) atomicAdd(&counts[q * 256 + threadIdx.x], t);
     }
 }
