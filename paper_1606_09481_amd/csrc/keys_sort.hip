@@ -97,7 +97,7 @@ void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStrea
 //
 // The digit counts of every pass do not depend on the order of the keys, so
 // one read of the keys gives them all (k_digit_counts).  A pass then takes
-// its 4096-key tiles in ticket order (an atomic counter: a workgroup only
+// its 6144-key tiles in ticket order (an atomic counter: a workgroup only
 // ever waits for tiles whose tickets were drawn before its own, by
 // workgroups already running), ranks its keys stably per digit (per-wave
 // ballots), and finds, per digit, how many keys of that digit the earlier
@@ -113,7 +113,7 @@ void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStrea
 // on, so no workgroup waits forever.
 // ---------------------------------------------------------------------------
 constexpr int S_THREADS = 256;
-constexpr int S_ITEMS = 16;
+constexpr int S_ITEMS = 24;  // 6144-key tiles: fewer tiles to look back over
 constexpr int S_TILE = S_THREADS * S_ITEMS;
 constexpr int S_MAX_PASSES = 4;
 constexpr uint64_t ST_LOCAL = 1ull << 62, ST_TOTAL = 2ull << 62, ST_VALUE = (1ull << 62) - 1;
