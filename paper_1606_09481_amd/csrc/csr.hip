@@ -4,6 +4,8 @@
 // keys) orders them, so within a row the neighbours keep the order of the
 // pairs in the list; the row pointers are the first entry of each row in the
 // sorted rows.
+#include <algorithm>
+
 #include "rhg_kernels.h"
 
 namespace rhgk {
@@ -11,26 +13,49 @@ using namespace rhgd;
 
 // Entries 2e and 2e + 1 of pair e: (lo, hi) and (hi, lo).  An end outside
 // 0..n-1 raises *err (the caller stops before sorting) and is written as 0,
-// so no later step indexes outside row_ptr.
+// so no later step indexes outside row_ptr.  The row digits of every sort
+// pass are counted on the way (the sort then needs no counting read of its
+// own): LDS histograms in 8 copies, lane l counting into copy l mod 8, since
+// a query's row repeats over runs of pairs and would otherwise put the lanes
+// of an LDS atomic on one bin; one global add per bin and workgroup.
+constexpr int DIR_COPIES = 8;
 __global__ __launch_bounds__(256) void k_directed(const int2 *pairs, uint64_t m, uint32_t n, uint2 *rows,
-                                                  uint2 *nbrs, uint32_t *err) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const int2 p = pairs[e];
-    uint32_t a = (uint32_t)p.x, b = (uint32_t)p.y;
-    if (a >= n || b >= n) {
-        atomicOr(err, 1u);
-        a = b = 0u;
+                                                  uint2 *nbrs, uint32_t *err, int passes, uint32_t *counts) {
+    __shared__ uint32_t h[DIR_COPIES][4][256];
+    const int c = threadIdx.x & (DIR_COPIES - 1);
+    for (int q = 0; q < 4; ++q)
+        for (int x = 0; x < DIR_COPIES; ++x) h[x][q][threadIdx.x] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
+        const int2 p = pairs[e];
+        uint32_t a = (uint32_t)p.x, b = (uint32_t)p.y;
+        if (a >= n || b >= n) {
+            bad = true;
+            a = b = 0u;
+        }
+        rows[e] = make_uint2(a, b);
+        nbrs[e] = make_uint2(b, a);
+        for (int q = 0; q < passes; ++q) {
+            atomicAdd(&h[c][q][(a >> (8 * q)) & 255u], 1u);
+            atomicAdd(&h[c][q][(b >> (8 * q)) & 255u], 1u);
+        }
     }
-    rows[e] = make_uint2(a, b);
-    nbrs[e] = make_uint2(b, a);
+    if (bad) atomicOr(err, 1u);
+    __syncthreads();
+    for (int q = 0; q < passes; ++q) {
+        uint32_t t = 0;
+        for (int x = 0; x < DIR_COPIES; ++x) t += h[x][q][threadIdx.x];
+        if (t) atomicAdd(&counts[q * 256 + threadIdx.x], t);
+    }
 }
 
-void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err,
-              hipStream_t st) {
+void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err, int passes,
+              uint32_t *counts, hipStream_t st) {
     if (!m) return;
-    hipLaunchKernelGGL(k_directed, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pairs, m, (uint32_t)n,
-                       (uint2 *)rows, (uint2 *)nbrs, err);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(2048, (m + 255) / 256);
+    hipLaunchKernelGGL(k_directed, dim3(blocks), dim3(256), 0, st, pairs, m, (uint32_t)n, (uint2 *)rows, (uint2 *)nbrs,
+                       err, passes, counts);
 }
 
 // row_ptr[v] = first sorted entry with row >= v, v = 0..n: entry i writes the

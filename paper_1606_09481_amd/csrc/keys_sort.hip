@@ -315,19 +315,32 @@ size_t sort_scratch_bytes(uint64_t n) {
 
 int sort_passes(int bits) { return std::min((bits + 7) / 8, S_MAX_PASSES); }
 
+void sort_prepare(void *scratch, uint64_t n, int bits, hipStream_t st) {
+    const uint64_t ntiles = (n + S_TILE - 1) / S_TILE;
+    const size_t status_bytes = (size_t)sort_passes(bits) * ntiles * 256 * sizeof(uint64_t);
+    // tickets, error flag, digit counts and the status words of every pass start at zero
+    (void)hipMemsetAsync(scratch, 0, 256 + S_MAX_PASSES * 256 * sizeof(uint32_t) + status_bytes, st);
+}
+
+uint32_t *sort_counts(void *scratch) { return sort_scratch(scratch, 0).counts; }
+
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                 int bits, hipStream_t st, bool copy_back) {
     if (n < 2) return;
-    const uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
-    int passes = (bits + 7) / 8;
-    if (passes > S_MAX_PASSES) passes = S_MAX_PASSES;
-    const SortScratch x = sort_scratch(scratch, ntiles);
-    const size_t status_bytes = (size_t)passes * ntiles * 256 * sizeof(uint64_t);
-    // tickets, error flag, digit counts and the status words of every pass start at zero
-    (void)hipMemsetAsync(scratch, 0, 256 + S_MAX_PASSES * 256 * sizeof(uint32_t) + status_bytes, st);
+    sort_prepare(scratch, n, bits, st);
     // few workgroups: each adds its 4 x 256 counts to the same global words
     const unsigned cblocks = (unsigned)std::min<uint64_t>(256, (n + S_THREADS * 16 - 1) / (S_THREADS * 16));
-    hipLaunchKernelGGL(k_digit_counts, dim3(cblocks), dim3(S_THREADS), 0, st, keys, (uint32_t)n, passes, x.counts);
+    hipLaunchKernelGGL(k_digit_counts, dim3(cblocks), dim3(S_THREADS), 0, st, keys, (uint32_t)n, sort_passes(bits),
+                       sort_counts(scratch));
+    sort_by_counts(keys, vals, keys_tmp, vals_tmp, scratch, n, bits, st, copy_back);
+}
+
+void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
+                    int bits, hipStream_t st, bool copy_back) {
+    if (n < 2) return;
+    const uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
+    const int passes = sort_passes(bits);
+    const SortScratch x = sort_scratch(scratch, ntiles);
     uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_sort_pass, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, 8 * p,

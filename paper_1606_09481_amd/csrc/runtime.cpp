@@ -803,13 +803,14 @@ extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t
         uint32_t *r0 = odd ? rows2 : rows, *c0 = odd ? nbrs2 : (uint32_t *)col;
         uint32_t *r1 = odd ? rows : rows2, *c1 = odd ? (uint32_t *)col : nbrs2;
         RHG_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), st));
-        rhgk::directed((const int2 *)pairs, m, n, r0, c0, err, st);
+        rhgk::sort_prepare(scr, len, bits, st);  // the expansion adds the sort's digit counts
+        rhgk::directed((const int2 *)pairs, m, n, r0, c0, err, rhgk::sort_passes(bits), rhgk::sort_counts(scr), st);
         uint32_t *err_host = (uint32_t *)((char *)c->pinned + 1036);
         RHG_HIP(hipMemcpyAsync(err_host, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         RHG_HIP(hipStreamSynchronize(st));
         if (*err_host != 0) return RHG_EINVAL;  // an end outside 0..n-1: nothing sorted or written
         // stable by row: a row's neighbours keep the order of their pairs
-        rhgk::radix_sort(r0, c0, r1, c1, scr, len, bits, st, false);
+        rhgk::sort_by_counts(r0, c0, r1, c1, scr, len, bits, st, false);
         RHG_HIP(hipMemcpyAsync(err_host, rhgk::sort_error_flag(scr), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     }
     rhgk::row_pointers(rows, len, n, row_ptr, st);
