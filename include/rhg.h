@@ -63,7 +63,11 @@ typedef enum {
  *   n          number of points, 2 <= n < 2^31 (RHG_ERANGE above: int32 indices).
  *   alpha      dispersion, > 0; with kbar (R <= 0) it must be > 1/2.
  *   kbar       target average degree, used when R <= 0: R = getTargetRadius(n, alpha, kbar).
- *   R          disk radius; R > 0 overrides kbar.  FP32_RECHECK needs R <= 43.
+ *   R          disk radius; R > 0 overrides kbar.  0 < R <= 354 (RHG_EINVAL
+ *              beyond: the FP64 distance test forms 2 sinh r_u sinh r_w, which
+ *              must be finite for every pair of points, up to e^{2R}/2 <
+ *              DBL_MAX); the sampler also needs sinh(alpha R / 2) finite.
+ *              FP32_RECHECK needs R <= 43.
  *   seed       SplitMix64 seed; point i uses outputs 2i (angle) and 2i+1 (radius).
  *   precision  RHG_FP64 or RHG_FP32_RECHECK.
  *   num_bands  number of slabs B, 0 = max(1, ceil(log2 n) - 8); 1 <= B <= 32.
@@ -167,8 +171,9 @@ rhg_status rhg_band_boundaries(double R, uint32_t num_bands, double band_ratio, 
 rhg_status rhg_generate(rhg_ctx *ctx, const rhg_params *params, rhg_graph **out);
 
 /* Same for caller coordinates: theta[n] in [0, 2pi] (2pi meaning fl(2*pi)),
- * r[n] in [0, R], FP64, host or device memory (coords_on_device = 0/1; device
- * arrays are only read).  Edges use the positions in these arrays. */
+ * r[n] in [0, R], 0 < R <= 354, FP64, host or device memory (coords_on_device
+ * = 0/1; device arrays are only read).  Edges use the positions in these
+ * arrays. */
 rhg_status rhg_generate_from_coords(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r, double R,
                                     rhg_precision precision, int coords_on_device, rhg_graph **out);
 
@@ -197,8 +202,8 @@ rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta
  * exactly (Theorem 1).  A zero step leaves the coordinate bit for bit as it
  * is, so nodes with tau_phi = tau_r = 0 stay put.
  * The arrays are owned by the caller and must not
- * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha or R not
- * finite and positive; RHG_ERANGE: n >= 2^31.  Regenerate the graph of the moved points with
+ * overlap.  RHG_EINVAL: null context, null arrays with n > 0, alpha not
+ * finite and positive, R outside (0, 354]; RHG_ERANGE: n >= 2^31.  Regenerate the graph of the moved points with
  * rhg_generate_from_coords (coords_on_device = 1), or update it with
  * rhg_update_after_move. */
 rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R, double *theta, double *r,

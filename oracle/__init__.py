@@ -58,9 +58,9 @@ def lib():
         L.orc_band_of_radius.argtypes = [d, vp, i32]
         L.orc_splitmix64.restype = u64
         L.orc_splitmix64.argtypes = [u64, u64]
-        L.orc_sample.restype = None
+        L.orc_sample.restype = i32
         L.orc_sample.argtypes = [u64, d, d, u64, vp, vp]
-        L.orc_sample_range.restype = None
+        L.orc_sample_range.restype = i32
         L.orc_sample_range.argtypes = [u64, u64, d, d, u64, vp, vp]
         L.orc_table.restype = None
         L.orc_table.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp]
@@ -163,6 +163,9 @@ def sample(n: int, alpha: float, R: float, seed: int, threads: int = 0) -> Tuple
     theta = np.empty(n, dtype=np.float64)
     r = np.empty(n, dtype=np.float64)
     L = lib()
+    # an empty range only checks the parameters
+    if L.orc_sample_range(0, 0, float(alpha), float(R), int(seed), _ptr(theta), _ptr(r)) != 0:
+        raise ValueError("outside the sampler's domain (R in (0, 354], sinh(alpha R / 2) finite)")
     ranges, threads = _chunks(n, threads)
     _run([lambda a=a, b=b: L.orc_sample_range(a, b, float(alpha), float(R), int(seed), _ptr(theta), _ptr(r))
           for a, b in ranges], threads)
@@ -195,7 +198,12 @@ def is_edge(tab: np.ndarray, u: int, v: int, K: float) -> bool:
                                   int(u), int(v), float(K)))
 
 
+EDOMAIN = -2  # R outside (0, 354] (or K = cosh R beyond cosh 354), a query index out of range
+
+
 def _take(ptr: ctypes.c_void_p, m: int) -> np.ndarray:
+    if m == EDOMAIN:
+        raise ValueError("outside the oracle's domain (R in (0, 354], queries in 0..n-1)")
     if m < 0:
         raise MemoryError("oracle allocation failed")
     out = np.empty((m, 2), dtype=np.int32)

@@ -53,6 +53,16 @@
 #define ORC_PI 3.14159265358979323846
 #define ORC_TWO_PI (2.0 * 3.14159265358979323846) /* fl(2*pi): the angle period used by the sampler */
 
+/* Domain of the disk radius.  Eq. 3 is evaluated below as
+ * cosh(r_u - r_v) + 2 sinh r_u sinh r_v sin^2(dtheta/2); every product in it
+ * must be finite for all pairs in the disk, or two coincident points on the
+ * rim (sin = 0) would meet inf * 0 = NaN and be declared non-adjacent.  The
+ * largest product is 2 sinh^2 R ~ e^{2R}/2, finite while 2R < ln(2 DBL_MAX)
+ * = 710.48.  Radii up to 354 are accepted (a factor e^{2.4} below overflow);
+ * beyond, the entry points return ORC_EDOMAIN. */
+#define ORC_R_MAX 354.0
+#define ORC_EDOMAIN (-2)
+
 /* ------------------------------------------------------------------------- */
 /* getTargetRadius (Sec. III-B).                                              */
 /* ------------------------------------------------------------------------- */
@@ -152,8 +162,10 @@ static double orc_unit(uint64_t x) { return (double)(x >> 11) * (1.0 / 900719925
  * radius: inverse of F(r) = (cosh(alpha r) - 1)/(cosh(alpha R) - 1)
  *       = sinh^2(alpha r / 2) / sinh^2(alpha R / 2),
  *   i.e. r = 2 asinh( sqrt(u) sinh(alpha R / 2) ) / alpha, clamped to [0, R]. */
-void orc_sample_range(uint64_t i0, uint64_t i1, double alpha, double R, uint64_t seed, double *theta, double *r) {
+int orc_sample_range(uint64_t i0, uint64_t i1, double alpha, double R, uint64_t seed, double *theta, double *r) {
+    if (!(R > 0.0 && R <= ORC_R_MAX) || !(alpha > 0.0) || !isfinite(alpha)) return ORC_EDOMAIN;
     double sR = sinh(alpha * R / 2.0);
+    if (!isfinite(sR)) return ORC_EDOMAIN; /* the inverse CDF needs sinh(alpha R / 2) */
     for (uint64_t i = i0; i < i1; ++i) {
         double u1 = orc_unit(orc_splitmix64(seed, 2 * i));
         double u2 = orc_unit(orc_splitmix64(seed, 2 * i + 1));
@@ -161,10 +173,11 @@ void orc_sample_range(uint64_t i0, uint64_t i1, double alpha, double R, uint64_t
         double ri = 2.0 * asinh(sqrt(u2) * sR) / alpha;
         r[i] = ri > R ? R : ri;
     }
+    return 0;
 }
 
-void orc_sample(uint64_t n, double alpha, double R, uint64_t seed, double *theta, double *r) {
-    orc_sample_range(0, n, alpha, R, seed, theta, r);
+int orc_sample(uint64_t n, double alpha, double R, uint64_t seed, double *theta, double *r) {
+    return orc_sample_range(0, n, alpha, R, seed, theta, r);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -244,8 +257,13 @@ void orc_free(void *p) { free(p); }
 /* Brute force: every pair i < j (the plain definition of the edge set).      */
 /* Output sorted lexicographically by construction.                           */
 /* ------------------------------------------------------------------------- */
+/* K = cosh R with R in the accepted domain (0, ORC_R_MAX]. */
+static int orc_K_in_domain(double K) { return K > 1.0 && K <= cosh(ORC_R_MAX); }
+
 int64_t orc_brute(int64_t n, const double *ep, const double *em, const double *sh, const double *hs,
                   const double *hc, double K, int32_t **out) {
+    *out = NULL;
+    if (!orc_K_in_domain(K)) return ORC_EDOMAIN;
     orc_tab t = {ep, em, sh, hs, hc};
     orc_buf b = {0};
     for (int64_t i = 0; i < n; ++i)
@@ -301,6 +319,9 @@ int64_t orc_brute_rows(int64_t n, const double *ep, const double *em, const doub
                        const double *hc, double K, const int64_t *queries, int64_t nq, int nthreads,
                        int32_t **out) {
     *out = NULL;
+    if (!orc_K_in_domain(K)) return ORC_EDOMAIN;
+    for (int64_t k = 0; k < nq; ++k)
+        if (queries[k] < 0 || queries[k] >= n) return ORC_EDOMAIN;
     orc_rows_ctx X;
     memset(&X, 0, sizeof X);
     X.n = n; X.nq = nq; X.q = queries; X.K = K; X.next = 0;
@@ -476,6 +497,7 @@ int64_t orc_band_sweep(int64_t n, const double *theta, const double *r, const do
                        int nthreads, int64_t q0, int64_t q1, int32_t **out, uint64_t *candidates_out) {
     *out = NULL;
     if (B < 1 || n < 0 || q0 < 0 || q1 > n || q0 > q1) return -1;
+    if (!(R > 0.0 && R <= ORC_R_MAX) || !orc_K_in_domain(K)) return ORC_EDOMAIN;
     double *c = (double *)malloc((size_t)(B + 1) * sizeof(double));
     int *band = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
     int64_t *band_off = (int64_t *)calloc((size_t)B + 1, sizeof(int64_t));

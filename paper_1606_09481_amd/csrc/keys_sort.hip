@@ -315,6 +315,8 @@ size_t sort_scratch_bytes(uint64_t n) {
 
 int sort_passes(int bits) { return std::min((bits + 7) / 8, S_MAX_PASSES); }
 
+uint64_t sort_max_keys() { return (1ull << 32) - (uint64_t)S_TILE; }
+
 void sort_prepare(void *scratch, uint64_t n, int bits, hipStream_t st) {
     const uint64_t ntiles = (n + S_TILE - 1) / S_TILE;
     const size_t status_bytes = (size_t)sort_passes(bits) * ntiles * 256 * sizeof(uint64_t);

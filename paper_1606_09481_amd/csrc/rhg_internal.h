@@ -116,6 +116,10 @@ inline uint64_t algorithmic_bytes(const Plan &p) {
 }
 
 rhg_status describe(const Request &rq, Plan &pl);
+// Largest disk radius R accepted by every entry point (the FP64 distance test
+// stays finite for all pairs of points up to it).
+constexpr double R_MAX = 354.0;
+bool radius_in_domain(double R);
 rhg_status request_from_params(const rhg_params *p, Request &rq);
 // Average degree the model approximation gives for (n, alpha, R) (n when alpha <= 1/2).
 double expected_degree(uint64_t n, double alpha, double R);

@@ -26,6 +26,9 @@ void band_starts(const uint32_t *keys, uint64_t n, int B, uint32_t *bs, hipStrea
 // whole spin budget (never expected; the sorted output is then invalid).
 uint32_t *sort_error_flag(void *scratch);
 size_t sort_scratch_bytes(uint64_t n);
+// Most keys one sort takes: tile positions are formed in 32 bits, and the
+// last tile must end at or below 2^32.
+uint64_t sort_max_keys();
 void radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                 int bits, hipStream_t st, bool copy_back = true);
 int sort_passes(int bits);

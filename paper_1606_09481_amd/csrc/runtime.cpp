@@ -266,6 +266,15 @@ rhg_status hip_status(hipError_t e) {
     type *var = (type *)c->buf((slot), sizeof(type) * (size_t)(count));  \
     if (!var) return RHG_ENOMEM
 
+// Largest disk radius accepted.  The distance test forms (2 sinh r_u) sinh r_w,
+// about e^{r_u + r_w} / 2, which must stay finite for every pair of points
+// in the disk: at r_u = r_w = R that needs e^{2R} < 2 DBL_MAX, R < 355.23.
+// Past it a pair of coincident points on the rim would give inf * 0 = NaN
+// and be declared non-adjacent.  354 leaves a factor e^{2.4} of headroom for
+// the rounding of sinh; every table entry (e^{+-r}, sinh r) and cosh R are
+// then finite as well.
+bool radius_in_domain(double R) { return R > 0.0 && R <= R_MAX; }
+
 int ceil_log2(uint64_t x) {
     int b = 0;
     while ((1ull << b) < x) ++b;
@@ -278,10 +287,12 @@ constexpr uint64_t N_MAX = 1ull << 31;
 
 rhg_status describe(const Request &rq, Plan &pl) {
     if (rq.n < 2 || rq.n >= N_MAX) return rq.n < 2 ? RHG_EINVAL : RHG_ERANGE;
-    if (!(rq.R > 0.0) || !std::isfinite(rq.R) || rq.R > 700.0) return RHG_EINVAL;
+    if (!radius_in_domain(rq.R)) return RHG_EINVAL;
     if (rq.precision != RHG_FP64 && rq.precision != RHG_FP32_RECHECK) return RHG_EINVAL;
     if (rq.precision == RHG_FP32_RECHECK && rq.R > 43.0) return RHG_EINVAL;
     if (rq.mode == SRC_SEED && !(rq.alpha > 0.0 && std::isfinite(rq.alpha))) return RHG_EINVAL;
+    // the sampler inverts Eq. 1's radius law through sinh(alpha R / 2)
+    if (rq.mode == SRC_SEED && !std::isfinite(std::sinh(rq.alpha * rq.R / 2.0))) return RHG_EINVAL;
     int B = rq.num_bands ? (int)rq.num_bands : default_bands(rq.n);
     double p = rq.band_ratio > 0.0 ? rq.band_ratio : 0.9;
     if (B < 1 || B > MAX_BANDS) return RHG_EINVAL;
@@ -784,6 +795,7 @@ extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     if (!c || n < 1 || !row_ptr || (m && (!pairs || !col))) return RHG_EINVAL;
     if (n >= N_MAX || m >= (1ull << 31)) return RHG_ERANGE;  // rows and entries indexed in 32 bits
+    if (2 * m > rhgk::sort_max_keys()) return RHG_ERANGE;     // the sort's tile positions are 32-bit
     RHG_HIP(hipSetDevice(c->device));
     (void)hipGetLastError();
     const hipStream_t st = c->stream;
@@ -797,11 +809,13 @@ extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t
         void *scr = c->buf(S_CSRSCR, rhgk::sort_scratch_bytes(len));
         if (!rows || !rows2 || !nbrs2 || !err || !scr) return RHG_ENOMEM;
         // the sorted entries must end in (rows, col): with an odd number of
-        // passes they start in the other buffers, so no copy back is needed
+        // passes they start in the other buffers, so no copy back is needed;
+        // with an even number the neighbours start in nbrs2 too (col is not
+        // written before the ends are checked) and end there, copied to col
         const int bits = std::max(1, ceil_log2(n));
         const bool odd = rhgk::sort_passes(bits) % 2 == 1;
-        uint32_t *r0 = odd ? rows2 : rows, *c0 = odd ? nbrs2 : (uint32_t *)col;
-        uint32_t *r1 = odd ? rows : rows2, *c1 = odd ? (uint32_t *)col : nbrs2;
+        uint32_t *r0 = odd ? rows2 : rows, *c0 = nbrs2;
+        uint32_t *r1 = odd ? rows : rows2, *c1 = (uint32_t *)col;
         RHG_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), st));
         rhgk::sort_prepare(scr, len, bits, st);  // the expansion adds the sort's digit counts
         rhgk::directed((const int2 *)pairs, m, n, r0, c0, err, rhgk::sort_passes(bits), rhgk::sort_counts(scr), st);
@@ -811,6 +825,7 @@ extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t
         if (*err_host != 0) return RHG_EINVAL;  // an end outside 0..n-1: nothing sorted or written
         // stable by row: a row's neighbours keep the order of their pairs
         rhgk::sort_by_counts(r0, c0, r1, c1, scr, len, bits, st, false);
+        if (!odd) RHG_HIP(hipMemcpyAsync(col, nbrs2, sizeof(uint32_t) * len, hipMemcpyDeviceToDevice, st));
         RHG_HIP(hipMemcpyAsync(err_host, rhgk::sort_error_flag(scr), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     }
     rhgk::row_pointers(rows, len, n, row_ptr, st);
@@ -824,7 +839,7 @@ extern "C" rhg_status rhg_move(rhg_ctx *ctx, uint64_t n, double alpha, double R,
                                const double *tau_phi, double *tau_r) {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     if (!c) return RHG_EINVAL;
-    if (!(std::isfinite(alpha) && alpha > 0.0 && std::isfinite(R) && R > 0.0)) return RHG_EINVAL;
+    if (!(std::isfinite(alpha) && alpha > 0.0 && radius_in_domain(R))) return RHG_EINVAL;
     if (n == 0) return RHG_OK;
     if (!theta || !r || !tau_phi || !tau_r) return RHG_EINVAL;
     if (n >= (1ull << 31)) return RHG_ERANGE;  // one thread per node in one launch

@@ -114,3 +114,14 @@ def test_size_limit(lib):
             rhg.rhg_server_estimate_bytes(rhg.params(n, 0.75, kbar=10))
         assert ei.value.status == rhg.RHG_ERANGE
 
+
+def test_csr_size_limit(lib):
+    """rhg_csr_from_pairs sorts 2m directed entries with 32-bit tile positions:
+    2m above 2^32 - 6144 (the last tile must end at or below 2^32) is refused
+    with RHG_ERANGE by the host-side size checks, which come before anything
+    reads the context, so a non-null placeholder stands in for one here."""
+    dummy = ctypes.c_void_p(1)
+    rp = ctypes.c_void_p(8)
+    for m in ((1 << 31) - 3000, (1 << 31) - 1):
+        st = lib.rhg_csr_from_pairs(dummy, 1000, ctypes.c_void_p(8), m, rp, ctypes.c_void_p(8))
+        assert st == rhg.RHG_ERANGE, m

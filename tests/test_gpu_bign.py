@@ -18,9 +18,30 @@ import numpy as np
 import pytest
 
 from paper_1606_09481_amd import rhg
-from test_gpu_fullsize import _device_view, _incident_device
+from test_gpu_fullsize import _device_view
 
 pytestmark = pytest.mark.gpu
+
+
+def _incident_device(out, m, rows, n):
+    """Canonical keys of the device edges touching `rows`, plus whole-output checks."""
+    import torch
+    flag = torch.zeros(n, dtype=torch.bool, device=out.device)
+    flag[torch.as_tensor(rows, device=out.device)] = True
+    sel = []
+    chunk = 1 << 25
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        e = out[2 * a:2 * b].view(-1, 2).long()
+        assert bool((e[:, 0] < e[:, 1]).all()), "lo < hi"
+        assert int(e[:, 0].min()) >= 0 and int(e[:, 1].max()) < n, "indices in range"
+        mk = flag[e[:, 0]] | flag[e[:, 1]]
+        sel.append(e[mk].cpu())
+    e = torch.cat(sel).numpy()
+    k = (e[:, 0] << 32) | e[:, 1]
+    ks = np.sort(k)
+    assert np.all(ks[1:] != ks[:-1]), "each edge once"
+    return ks
 
 
 def _rows(r, n, rng, k_rand=32, k_end=8):

@@ -98,10 +98,13 @@ def test_csr_empty_and_rejects(ctx):
     import torch
     ptr, col = _csr(ctx, 1000, 0, 0)
     assert np.all(ptr == 0)
-    bad = torch.tensor([0, 1, 2, 1000], dtype=torch.int32, device="cuda")
-    row_ptr = torch.zeros(1001, dtype=torch.int64, device="cuda")
-    colb = torch.zeros(4, dtype=torch.int32, device="cuda")
-    with pytest.raises(rhg.RhgError) as ei:
-        rhg.rhg_csr_from_pairs(ctx, 1000, bad, 2, row_ptr, colb)
-    assert ei.value.status == rhg.RHG_EINVAL
-    assert int(row_ptr.abs().sum()) == 0  # nothing written
+    # n = 1000 (10 row bits: 2 sort passes) and n = 300 (9 bits: 2 passes)
+    # leave the neighbours where they started; n = 100 (7 bits: 1 pass) does not
+    for n in (1000, 300, 100):
+        bad = torch.tensor([0, 1, 2, n], dtype=torch.int32, device="cuda")
+        row_ptr = torch.full((n + 1,), -7, dtype=torch.int64, device="cuda")
+        colb = torch.full((4,), -5, dtype=torch.int32, device="cuda")
+        with pytest.raises(rhg.RhgError) as ei:
+            rhg.rhg_csr_from_pairs(ctx, n, bad, 2, row_ptr, colb)
+        assert ei.value.status == rhg.RHG_EINVAL
+        assert bool((row_ptr == -7).all()) and bool((colb == -5).all())  # nothing written

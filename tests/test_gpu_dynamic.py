@@ -141,13 +141,16 @@ def test_graph_of_moved_points(ctx, orc):
     for _ in range(3):
         rhg.rhg_move(ctx, dth, dr, dtp, dtr, alpha, R)
     g = rhg.rhg_generate_from_coords(ctx, dth, dr, R)
-    e = rhg.rhg_graph_copy_edges(g)
-    rhg.rhg_graph_free(g)
-    th2, r2 = _host(dth), _host(dr)
-    t = orc.table(th2, r2)
-    K = math.cosh(R)
+    try:
+        e = rhg.rhg_graph_copy_edges(g)
+        ref, (th2, r2, t, K) = parity.oracle_edges(orc, g, rhg)
+    finally:
+        rhg.rhg_graph_free(g)
+    assert np.array_equal(th2, _host(dth)) and np.array_equal(r2, _host(dr))
+    assert K == math.cosh(R)
     parity.assert_valid(e, n)
-    parity.assert_same_up_to_rounding(e, orc.band_sweep(th2, r2, t, R, K), t, K)
+    parity.assert_same(e, ref)
+    parity.assert_table_close(orc, th2, r2, t)
 
 
 def test_move_rejects(ctx):

@@ -1,5 +1,6 @@
 """Parity at the benchmark sizes, in the launch configuration the benchmark
-times (rhg_count + rhg_emit into one preallocated device buffer).
+times (rhg_count + rhg_emit into one preallocated device buffer), on whole
+edge sets.
 
 Workloads: n = 10^7, alpha = 0.75, kbar = 100 (about 5.0e8 edges), the
 exponent sweep n = 4*10^6, kbar = 64, alpha in {0.55, 1.0, 1.5} (alpha = 0.55
@@ -8,39 +9,30 @@ kbar = 16 (hub batches whose windows in one slab add up to near 2^32
 candidates, the most a 32-bit scan holds), both precision forms.  Larger n:
 test_gpu_bign.py.
 
-The oracle cannot list 10^8..10^9 edges pair by pair, so it answers for
-sampled vertices: every neighbour of 96 random vertices, of the 16 innermost
-points (the hubs, whose windows span whole slabs) and of the 16 outermost
-ones, by the all-pairs definition on those rows.  Checked:
-  * table mode (the oracle's own table handed to the device): the edges
-    incident to the sampled vertices are exactly the oracle's;
-  * seeded mode (the device samples and builds its table): the same, except
-    pairs within the table rounding of the threshold (reported, bounded);
-  * the whole output: lo < hi, indices in range, FP32+recheck bytes equal to
-    FP64 bytes, m within 5% of n kbar / 2.
+Each case compares whole edge sets, sorted as 64-bit keys lo * 2^32 + hi on
+the device:
+  * seeded mode, as the benchmark runs it: the device samples the points and
+    builds its own table; the oracle's band sweep over every query, on the
+    table bits the device exported (rhg_graph_copy_points), must give the
+    identical edge set;
+  * FP32 filter + FP64 recheck: byte-identical to the FP64 output;
+  * table mode: the oracle's own sample and host-libm table handed to the
+    device; the device edge set must equal the oracle's band sweep on that
+    table, in both precision forms.
+Also: lo < hi, indices in range, each edge once, m within 5% of n kbar / 2.
 """
 import math
+import time
 
 import numpy as np
 import pytest
 
-import parity
 from paper_1606_09481_amd import rhg
 
 pytestmark = pytest.mark.gpu
 
 CASES = [(10_000_000, 0.75, 100.0), (4_000_000, 0.55, 64.0), (4_000_000, 1.0, 64.0), (4_000_000, 1.5, 64.0),
          ((1 << 26) - 1, 0.55, 16.0)]  # hub batches just below 2^32 candidates per slab segment
-def _oracle_case(orc, n, alpha, kbar):
-    R = orc.target_radius(n, alpha, kbar)
-    th, r = orc.sample(n, alpha, R, 1)
-    t = orc.table(th, r)
-    rng = np.random.default_rng(n + int(1000 * alpha))
-    order = np.argsort(r, kind="stable")
-    rows = np.unique(np.concatenate([rng.choice(n, 96, replace=False), order[:16], order[-16:]]))
-    ref = orc.brute_rows(t, math.cosh(R), rows)
-    ref = np.unique(np.sort(ref.reshape(-1, 2), axis=1).astype(np.int64) @ np.array([1 << 32, 1], np.int64))
-    return R, th, r, t, rows, ref
 
 
 @pytest.fixture(scope="module")
@@ -51,27 +43,6 @@ def torch_ctx():
     c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
     yield c
     rhg.rhg_ctx_destroy(c)
-
-
-def _incident_device(out, m, rows, n):
-    """Canonical keys of the device edges touching `rows`, plus whole-output checks."""
-    import torch
-    flag = torch.zeros(n, dtype=torch.bool, device=out.device)
-    flag[torch.as_tensor(rows, device=out.device)] = True
-    sel = []
-    chunk = 1 << 25
-    for a in range(0, m, chunk):
-        b = min(m, a + chunk)
-        e = out[2 * a:2 * b].view(-1, 2).long()
-        assert bool((e[:, 0] < e[:, 1]).all()), "lo < hi"
-        assert int(e[:, 0].min()) >= 0 and int(e[:, 1].max()) < n, "indices in range"
-        mk = flag[e[:, 0]] | flag[e[:, 1]]
-        sel.append(e[mk].cpu())
-    e = torch.cat(sel).numpy()
-    k = (e[:, 0] << 32) | e[:, 1]
-    ks = np.sort(k)
-    assert np.all(ks[1:] != ks[:-1]), "each edge once"
-    return ks
 
 
 class _Dev:
@@ -86,56 +57,101 @@ def _device_view(ptr, count):
     return torch.as_tensor(_Dev(ptr, count), device="cuda")
 
 
-def _count_emit(ctx, p):
+def sorted_keys(pairs, m, n):
+    """Sorted keys lo * 2^32 + hi of m int32 pairs (a flat device or host
+    array of 2m), on the device, after checking lo < hi, the index range and
+    that no edge repeats."""
+    import torch
+    if isinstance(pairs, np.ndarray):
+        pairs = torch.from_numpy(np.ascontiguousarray(pairs).reshape(-1)).cuda()
+    k = torch.empty(m, dtype=torch.int64, device="cuda")
+    chunk = 1 << 26
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        e = pairs[2 * a:2 * b].view(-1, 2).long()
+        assert bool((e[:, 0] < e[:, 1]).all()), "lo < hi"
+        assert int(e[:, 0].min()) >= 0 and int(e[:, 1].max()) < n, "indices in range"
+        k[a:b] = (e[:, 0] << 32) | e[:, 1]
+        del e
+    k = torch.sort(k).values
+    assert m < 2 or bool((k[1:] > k[:-1]).all()), "each edge once"
+    return k
+
+
+def assert_same_sets(dev_keys, ref_keys, what):
+    import torch
+    same = len(dev_keys) == len(ref_keys) and bool(torch.equal(dev_keys, ref_keys))
+    if not same:
+        import numpy as _np
+        a, b = dev_keys.cpu().numpy(), ref_keys.cpu().numpy()
+        diff = _np.setxor1d(a, b)
+        raise AssertionError("%s: %d vs %d edges, %d pairs in one only, e.g. %s" % (
+            what, len(a), len(b), len(diff), [(int(x >> 32), int(x & 0xffffffff)) for x in diff[:5]]))
+
+
+def _count_emit(ctx, p, export_points=False):
     import torch
     plan, m = rhg.rhg_count(ctx, p)
-    out = torch.empty(2 * m + 2, dtype=torch.int32, device="cuda")
-    rhg.rhg_emit(ctx, plan, out, m + 1)
-    torch.cuda.synchronize()
-    st = rhg.rhg_graph_stats(plan)
-    R = rhg.rhg_graph_radius(plan)
-    rhg.rhg_graph_free(plan)
-    return out, m, st, R
+    try:
+        out = torch.empty(2 * m + 2, dtype=torch.int32, device="cuda")
+        rhg.rhg_emit(ctx, plan, out, m + 1)
+        torch.cuda.synchronize()
+        st = rhg.rhg_graph_stats(plan)
+        R = rhg.rhg_graph_radius(plan)
+        pts = rhg.rhg_graph_copy_points(plan) if export_points else None
+    finally:
+        rhg.rhg_graph_free(plan)
+    return out, m, st, R, pts
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("n,alpha,kbar", CASES)
 def test_fullsize(torch_ctx, orc, n, alpha, kbar):
     import torch
+    t0 = time.time()
     print("case", n, alpha, kbar, flush=True)
-    R, th, r, t, rows, ref = _oracle_case(orc, n, alpha, kbar)
-    K = math.cosh(R)
 
-    # table mode: identical table bits on both sides -> identical incident edges
-    for prec in (rhg.RHG_FP64, rhg.RHG_FP32_RECHECK):
-        g = rhg.rhg_generate_from_table(torch_ctx, th, r, t, R, prec)
-        try:
-            m = rhg.rhg_graph_num_edges(g)
-            got = _incident_device(_device_view(rhg.rhg_graph_edges_device(g), 2 * m), m, rows, n)
-        finally:
-            rhg.rhg_graph_free(g)
-        assert len(got) == len(ref) and np.array_equal(got, ref), \
-            "table mode, prec %d: %d incident edges vs %d in the oracle" % (prec, len(got), len(ref))
-    print("table mode exact:", len(ref), "incident edges of", len(rows), "vertices", flush=True)
-
-    # seeded, as the benchmark runs it
-    out64, m64, st64, R64 = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1))
-    assert R64 == R
+    # seeded, as the benchmark runs it, against the oracle on the exported bits
+    out64, m64, st64, R, (th, r, t, K) = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1),
+                                                     export_points=True)
+    assert R == orc.target_radius(n, alpha, kbar) or abs(R - orc.target_radius(n, alpha, kbar)) <= 1e-13 * R
+    assert K == math.cosh(R)
     assert abs(m64 - n * kbar / 2) <= 0.05 * n * kbar / 2
-    got = _incident_device(out64, m64, rows, n)
-    diff = np.setxor1d(got, ref)  # only pairs within the table rounding of K may differ
-    if len(diff):
-        u = (diff >> 32).astype(np.int64)
-        v = (diff & 0xffffffff).astype(np.int64)
-        V, bound = parity.ambiguity_bound(t, u, v)
-        assert not (np.abs(V - K) > bound).any(), "pairs far from the threshold decided differently"
-        assert len(diff) <= 16
-    print("seeded: ambiguous pairs", len(diff), "of", len(ref), flush=True)
-    out32, m32, st32, _ = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1,
-                                                            precision=rhg.RHG_FP32_RECHECK))
+    dev = sorted_keys(out64, m64, n)
+    ref = orc.band_sweep(th, r, t, R, K)
+    print("oracle sweep on the device's table: %d edges (%.0f s)" % (len(ref), time.time() - t0), flush=True)
+    assert_same_sets(dev, sorted_keys(ref, len(ref), n), "seeded FP64 vs oracle")
+    del ref, th, r, t
+    print("seeded: identical edge sets, %d edges" % m64, flush=True)
+
+    out32, m32, st32, _, _ = _count_emit(torch_ctx, rhg.params(n, alpha, kbar=kbar, seed=1,
+                                                               precision=rhg.RHG_FP32_RECHECK))
     assert m32 == m64
     assert bool(torch.equal(out32[:2 * m64], out64[:2 * m64])), "FP32+recheck bytes differ from FP64"
     assert st32["candidates"] == st64["candidates"]
     print("rechecks", st32["rechecks"], "of", st32["candidates"], "candidates", flush=True)
+    del out32, out64, dev
+    torch.cuda.empty_cache()
+
+    # table mode: the oracle's own sample and host-libm table, both precisions
+    tho, ro = orc.sample(n, alpha, R, 1)
+    to = orc.table(tho, ro)
+    ref = orc.band_sweep(tho, ro, to, R, K)
+    refk = sorted_keys(ref, len(ref), n)
+    del ref
+    print("oracle sweep on the host table: %d edges (%.0f s)" % (len(refk), time.time() - t0), flush=True)
+    for prec in (rhg.RHG_FP64, rhg.RHG_FP32_RECHECK):
+        g = rhg.rhg_generate_from_table(torch_ctx, tho, ro, to, R, prec)
+        try:
+            m = rhg.rhg_graph_num_edges(g)
+            got = sorted_keys(_device_view(rhg.rhg_graph_edges_device(g), 2 * m), m, n)
+        finally:
+            rhg.rhg_graph_free(g)
+        assert_same_sets(got, refk, "table mode, precision %d" % prec)
+        del got
+    print("table mode: identical edge sets (%.0f s)" % (time.time() - t0), flush=True)
+    del refk
+    torch.cuda.empty_cache()
 
 
 def _edge_checksum(out, m):
@@ -162,14 +178,14 @@ def test_fullsize_shares_partition_the_graph():
     p = rhg.params(10_000_000, 0.75, kbar=100.0, seed=1)
     c = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
     try:
-        out, m, st, _ = _count_emit(c, p)
+        out, m, st, _, _ = _count_emit(c, p)
         ref = _edge_checksum(out, m)
         del out
         S, m_sum, h_sum, cands = 8, 0, 0, []
         for k in range(S):
             rhg.rhg_ctx_set_option(c, rhg.RHG_OPT_SHARD_COUNT, S)
             rhg.rhg_ctx_set_option(c, rhg.RHG_OPT_SHARD_INDEX, k)
-            o, mk, sk, _ = _count_emit(c, p)
+            o, mk, sk, _, _ = _count_emit(c, p)
             e = o[:2 * mk].view(-1, 2)
             assert mk == 0 or bool((e[:, 0] < e[:, 1]).all())
             m_sum += mk

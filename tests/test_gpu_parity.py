@@ -4,9 +4,10 @@
   identical, bit for bit, for model, uniform and adversarial points, every
   slab count and ratio, both precision forms.
 * Seeded generation (rhg_generate): the device samples and builds its own
-  table; angles must equal the oracle's bit for bit, radii and table entries
-  within 2 ulp, and the edge sets agree except pairs within that rounding of
-  the threshold (reported, at most a handful).
+  table; angles must equal the oracle's sampler bit for bit, radii within 4
+  ulp and table entries within 2 ulp of the host libm, and the edge set must
+  be identical to the oracle's on the table bits the device used (exported
+  by rhg_graph_copy_points): no pair may differ.
 * FP32 filter + FP64 recheck gives byte-identical output to FP64.
 """
 import math
@@ -43,10 +44,7 @@ def _from_table(ctx, orc, th, r, R, prec=rhg.RHG_FP64):
     return _edges(g), t, st
 
 
-def _ulps(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return np.abs(a - b) / np.spacing(np.maximum(np.abs(a), np.abs(b)))
+_ulps = parity.ulps
 
 
 # ---------------------------------------------------------------- identical table bits
@@ -152,29 +150,55 @@ def test_seeded_points_match_oracle_sampler(ctx, orc, n, alpha, kbar, seed):
     assert K == math.cosh(R)
 
 
+def _seeded_exact(ctx, orc, p, sweep, check_sampler=True):
+    """Seeded generation against the oracle on the device's own table bits
+    (identical edge sets), plus the device table within 2 ulp of the host
+    libm and the angles equal to the oracle sampler's as separate checks."""
+    g = rhg.rhg_generate(ctx, p)
+    try:
+        e = rhg.rhg_graph_copy_edges(g)
+        st = rhg.rhg_graph_stats(g)
+        ref, (th, r, t, K) = parity.oracle_edges(orc, g, rhg, sweep=sweep)
+        R = rhg.rhg_graph_radius(g)
+    finally:
+        rhg.rhg_graph_free(g)
+    parity.assert_valid(e, p.n)
+    parity.assert_same(e, ref)
+    assert K == math.cosh(R)
+    if check_sampler:
+        tho, ro = orc.sample(p.n, p.alpha, R, p.seed)
+        assert np.array_equal(th, tho)
+        assert _ulps(r, ro).max() <= 4
+    parity.assert_table_close(orc, th, r, t)
+    return e, st
+
+
 def test_config1_seeded_vs_bruteforce(ctx, orc):
-    """n = 10^4, alpha = 1, kbar = 10, seed 1: the device's sampled graph vs the all-pairs oracle."""
+    """n = 10^4, alpha = 1, kbar = 10, seed 1: the device's sampled graph vs
+    the all-pairs oracle on the same table bits, identical."""
     n, alpha, kbar = 10_000, 1.0, 10
-    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, kbar=kbar, seed=1))
-    R = rhg.rhg_graph_radius(g)
-    assert abs(R - orc.target_radius(n, alpha, kbar)) <= 1e-13 * R
-    e = _edges(g)
-    th, r = orc.sample(n, alpha, R, 1)
-    t = orc.table(th, r)
-    ref = orc.brute(t, math.cosh(R))
-    parity.assert_valid(e, n)
-    parity.assert_same_up_to_rounding(e, ref, t, math.cosh(R))
+    R = orc.target_radius(n, alpha, kbar)
+    assert abs(rhg.rhg_target_radius(n, alpha, kbar) - R) <= 1e-13 * R
+    for prec in (rhg.RHG_FP64, rhg.RHG_FP32_RECHECK):
+        _seeded_exact(ctx, orc, rhg.params(n, alpha, kbar=kbar, seed=1, precision=prec), sweep=False)
 
 
-def test_golden_fixture(ctx):
+def test_golden_fixture(ctx, orc):
+    """The stored oracle graph (n = 2000, alpha = 1, kbar = 10, seed 1):
+    the device given the oracle's table reproduces it exactly, and the
+    seeded device graph equals the oracle on the device's own table bits."""
     path = os.path.join(os.path.dirname(__file__), "golden", "n2000_a1_k10_seed1.txt")
     with open(path) as f:
         f.readline()
         R = float.fromhex(f.readline().split()[1].split("=")[1])
         stored = np.loadtxt(f, dtype=np.int32).reshape(-1, 2)
-    g = rhg.rhg_generate(ctx, rhg.params(2000, 1.0, R=R, seed=1))
-    e = _edges(g)
-    assert len(parity.np.setxor1d(parity.canonical(e), parity.canonical(stored))) <= 2
+    th, r = orc.sample(2000, 1.0, R, 1)
+    for prec in (rhg.RHG_FP64, rhg.RHG_FP32_RECHECK):
+        e, _, _ = _from_table(ctx, orc, th, r, R, prec)
+        parity.assert_same(e, stored)
+    e, _ = _seeded_exact(ctx, orc, rhg.params(2000, 1.0, R=R, seed=1), sweep=False)
+    print("seeded vs stored fixture: %d pairs differ" % len(np.setxor1d(parity.canonical(e),
+                                                                         parity.canonical(stored))), flush=True)
 
 
 @pytest.mark.parametrize("prec", [rhg.RHG_FP64, rhg.RHG_FP32_RECHECK])
@@ -190,10 +214,8 @@ def test_config2_vs_band_oracle(ctx, orc, prec):
     e = _edges(g)
     parity.assert_valid(e, n)
     parity.assert_same(e, ref)
-    g = rhg.rhg_generate(ctx, rhg.params(n, alpha, R=R, seed=1, precision=prec))
-    st = rhg.rhg_graph_stats(g)
-    e2 = _edges(g)
-    parity.assert_same_up_to_rounding(e2, ref, t, K)
+    # seeded, as the benchmark runs it: identical to the band oracle on the device's table bits
+    _, st = _seeded_exact(ctx, orc, rhg.params(n, alpha, R=R, seed=1, precision=prec), sweep=True)
     if prec == rhg.RHG_FP32_RECHECK:
         print("config2 rechecks", st["rechecks"], "of", st["candidates"], flush=True)
 
@@ -261,7 +283,47 @@ def test_coords_on_device(ctx, orc):
     a = _edges(rhg.rhg_generate_from_coords(ctx, th, r, R))
     dth = torch.from_numpy(th).cuda()
     dr = torch.from_numpy(r).cuda()
-    b = _edges(rhg.rhg_generate_from_coords(ctx, dth, dr, R))
+    g = rhg.rhg_generate_from_coords(ctx, dth, dr, R)
+    try:
+        b = rhg.rhg_graph_copy_edges(g)
+        ref, (th2, r2, t2, K) = parity.oracle_edges(orc, g, rhg)
+    finally:
+        rhg.rhg_graph_free(g)
     assert np.array_equal(a, b)
-    t = orc.table(th, r)
-    parity.assert_same_up_to_rounding(a, orc.band_sweep(th, r, t, R, math.cosh(R)), t, math.cosh(R))
+    assert np.array_equal(th2, th) and np.array_equal(r2, r)  # the caller's coordinates, as passed
+    parity.assert_same(b, ref)
+    parity.assert_table_close(orc, th, r, t2)
+
+
+def test_largest_radius_coincident_rim_points(ctx, orc):
+    """R = 354, the largest radius accepted: coincident points on the rim are
+    adjacent (distance 0; 2 sinh^2 R is still finite, so no inf * 0), opposite
+    rim points are not, and the whole edge set equals the oracle's on the same
+    bits, computed on the device (coordinate form) and given (table form).
+    One ulp past 354 is refused."""
+    R = 354.0
+    rng = np.random.default_rng(354)
+    n = 3000
+    th = rng.random(n) * inputs.TWO_PI
+    r = R - rng.exponential(2.0, n).clip(0, R)
+    r[: n // 4] = R                                  # a quarter exactly on the rim
+    for k in range(0, 400, 2):                       # coincident pairs, many of them on the rim
+        th[k + 1], r[k + 1] = th[k], r[k]
+    th[500], r[500], th[501], r[501] = 1.0, R, 1.0 + math.pi, R  # opposite rim points
+    g = rhg.rhg_generate_from_coords(ctx, th, r, R)
+    try:
+        e = rhg.rhg_graph_copy_edges(g)
+        ref, (_, _, t, K) = parity.oracle_edges(orc, g, rhg, sweep=False)
+    finally:
+        rhg.rhg_graph_free(g)
+    parity.assert_valid(e, n)
+    parity.assert_same(e, ref)
+    keys = set(parity.canonical(e).tolist())
+    for k in range(0, 400, 2):
+        assert (k << 32) | (k + 1) in keys, "coincident points %d, %d not adjacent" % (k, k + 1)
+    assert (500 << 32) | 501 not in keys
+    e2, t2, _ = _from_table(ctx, orc, th, r, R)
+    parity.assert_same(e2, orc.brute(t2, math.cosh(R)))
+    with pytest.raises(rhg.RhgError) as ei:
+        rhg.rhg_generate_from_coords(ctx, th, r, float(np.nextafter(R, np.inf)))
+    assert ei.value.status == rhg.RHG_EINVAL

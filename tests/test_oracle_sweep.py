@@ -236,3 +236,52 @@ def test_golden_fixture(orc):
     th, r = orc.sample(2000, 1.0, R, 1)
     t = orc.table(th, r)
     assert np.array_equal(orc.sort_edges(orc.band_sweep(th, r, t, R, math.cosh(R))), stored)
+
+
+def _restricted(eb, rows):
+    """Row views (q, w) of the all-pairs edge list for each listed q, in list order."""
+    out = []
+    for q in rows:
+        a = eb[eb[:, 0] == q][:, 1]
+        b = eb[eb[:, 1] == q][:, 0]
+        w = np.sort(np.concatenate([a, b]))
+        out.append(np.stack([np.full(len(w), q, dtype=np.int32), w.astype(np.int32)], axis=1))
+    return np.concatenate(out) if out else np.empty((0, 2), np.int32)
+
+
+@pytest.mark.parametrize("case", ["model_hubs", "duplicates", "ragged", "adversarial"])
+def test_brute_rows_equals_brute_restricted(orc, case):
+    """The per-row all-pairs routine the full-size tests lean on is the plain
+    definition restricted to the listed rows: every neighbour of each listed
+    query, each once, in list order then increasing neighbour, with repeated
+    and adjacent listed rows, hubs, exact duplicate points and ragged n."""
+    rng = np.random.default_rng(17)
+    if case == "model_hubs":
+        n, alpha, kbar = 3001, 0.55, 8
+        R = orc.target_radius(n, alpha, kbar)
+        th, r = orc.sample(n, alpha, R, 7)
+    elif case == "duplicates":
+        n, R = 1500, 12.0
+        th, r = inputs.uniform_coords(n, R, 3)
+        for k in range(0, 300, 2):  # exact duplicate points, some of them listed rows
+            th[k + 1], r[k + 1] = th[k], r[k]
+    elif case == "ragged":
+        n, alpha, kbar = 997, 1.0, 12
+        R = orc.target_radius(n, alpha, kbar)
+        th, r = orc.sample(n, alpha, R, 9)
+    else:
+        n, R = 2000, 14.0
+        th, r = inputs.adversarial_coords(n, R, orc.boundaries(R, orc.default_bands(n), 0.9), 5)
+    t = orc.table(th, r)
+    K = math.cosh(R)
+    eb = orc.brute(t, K)
+    order = np.argsort(r, kind="stable")
+    rows = np.concatenate([order[:6], order[-4:], rng.choice(n, 20, replace=False), [0, 1, n - 1, 0]])
+    for threads in (1, 4):
+        got = orc.brute_rows(t, K, rows, threads=threads)
+        want = _restricted(eb, rows)
+        # the routine emits each row's neighbours in increasing order within the row
+        assert got.shape == want.shape and np.array_equal(got, want), (case, threads, got.shape, want.shape)
+    assert len(orc.brute_rows(t, K, np.array([], dtype=np.int64))) == 0
+    # hubs have many neighbours; at least one listed row is adjacent to another listed row
+    assert got.shape[0] > 0

@@ -4,8 +4,8 @@
   large ones on the multi-launch path, both precisions, kbar- and R-given,
   non-default slab settings -- returns for every request exactly the bytes
   rhg_generate returns for the same parameters alone.
-* One served small request against the all-pairs oracle on the oracle's own
-  sample of the same seed.
+* One served small request against the all-pairs oracle on the table bits
+  it used (identical edge sets).
 * Admission: estimated memory in flight never exceeds the budget; a request
   larger than the whole budget still runs (alone).
 * Ticket semantics: bounded waits, unknown and already-collected tickets.
@@ -102,16 +102,18 @@ def test_served_small_request_vs_bruteforce(orc):
     try:
         g, _ = rhg.rhg_server_wait(srv, rhg.rhg_server_submit(srv, rhg.params(n, alpha, kbar=kbar, seed=seed)))
         R = rhg.rhg_graph_radius(g)
+        ref, (th, r, t, K) = parity.oracle_edges(orc, g, rhg, sweep=False)
         e, _ = _edges(g)
         cnt = rhg.rhg_server_counters(srv)
     finally:
         rhg.rhg_server_destroy(srv)
     assert cnt["batched"] == 1
     parity.assert_valid(e, n)
-    th, r = orc.sample(n, alpha, R, seed)
-    t = orc.table(th, r)
-    ref = orc.brute(t, math.cosh(R))
-    parity.assert_same_up_to_rounding(e, ref, t, math.cosh(R))
+    parity.assert_same(e, ref)  # the all-pairs oracle on the table bits the served request used
+    assert K == math.cosh(R)
+    tho, _ = orc.sample(n, alpha, R, seed)
+    assert np.array_equal(th, tho)
+    parity.assert_table_close(orc, th, r, t)
 
 
 def _est_bytes(n, kbar):
