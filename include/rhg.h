@@ -259,6 +259,27 @@ rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t *pairs, ui
 rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_graph **plan, uint64_t *m);
 rhg_status rhg_emit(rhg_ctx *ctx, rhg_graph *plan, int32_t *dev_pairs, uint64_t capacity_pairs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rhg_count
+ * + rhg_emit of one seeded request in one call that allocates nothing.  All
+ * work arrays live in a fixed device array of 16 MiB that each device holds
+ * from the library's load until the process ends; its address is taken at
+ * rhg_ctx_create.  The whole generation is one launch of the one-launch
+ * small-request kernel (the serving path's), so the edge list is
+ * byte-identical to rhg_generate's / rhg_emit's for the same params.
+ *   params     as for rhg_generate; n <= 8192 (RHG_ERANGE above), any slab
+ *              count and precision.
+ *   dev_pairs  device int32 output, capacity_pairs pairs (NULL only with 0).
+ *   m          (host) receives the number of edges, also on RHG_ETRUNC.
+ * Synchronous on the context stream.  RHG_ETRUNC: m > capacity_pairs,
+ * nothing written.  RHG_EINVAL: as rhg_generate, or a query share set on the
+ * context.  Calls on one device share the fixed array: calls that overlap in
+ * time on one device (other contexts or threads) race, and the caller must
+ * serialise them; each call clears what it needs, so sequential calls are
+ * independent. */
+rhg_status rhg_generate_noalloc(rhg_ctx *ctx, const rhg_params *params, int32_t *dev_pairs,
+                                uint64_t capacity_pairs, uint64_t *m);
+
 /* ---- graph handle --------------------------------------------------------- */
 
 rhg_status rhg_graph_num_edges(const rhg_graph *g, uint64_t *m);

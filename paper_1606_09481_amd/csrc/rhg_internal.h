@@ -132,4 +132,22 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl);
 rhg_status run_emit(Ctx *c, Plan &pl, int2 *out);
 rhg_status generate(Ctx *c, const Request &rq, bool emit, Graph **out, uint64_t *m_out);
 
+// Scratch of one request on the one-launch path (small.hip): capacities of
+// the arrays whose size depends on the plan, and the bytes of all arrays.
+struct SmallLayout {
+    uint64_t bytes = 0;
+    uint64_t unit_cap = 0, win_cap = 0, btab_cap = 0;
+};
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+// Layout for n points in B slabs with room for unit_cap work units.
+SmallLayout small_layout_units(uint64_t n, int B, uint64_t unit_cap, bool fp32);
+// Fills the descriptor of one seeded request: geometry, source, and the
+// arrays of `lay` carved from `base` (device memory of lay.bytes);
+// stats: two zeroed device words for its counters.
+void small_fill_desc(rhgk::SmallDesc &D, const Plan &pl, const Request &rq, const SmallLayout &lay, char *base,
+                     unsigned long long *stats);
+// Per-device set-up of the fixed scratch of rhg_generate_noalloc (once per
+// device, with that device current); called by rhg_ctx_create.
+rhg_status noalloc_setup(int device);
+
 }  // namespace rhgi

@@ -173,6 +173,8 @@ extern "C" rhg_status rhg_ctx_create(int device, void *hip_stream, rhg_ctx **out
         return count == 0 ? RHG_EDEVICE : RHG_EINVAL;
     }
     if (hipSetDevice(device) != hipSuccess) return RHG_EDEVICE;
+    // the device address of this device's fixed scratch (rhg_generate_noalloc)
+    if (noalloc_setup(device) != RHG_OK) return RHG_EDEVICE;
     Ctx *c = new (std::nothrow) Ctx();
     if (!c) return RHG_ENOMEM;
     c->device = device;

@@ -9,7 +9,12 @@
 // between them.  The arithmetic (slab keys, windows, distance test, unit
 // walk) is the same code as the multi-launch path, so a request's edge list
 // is byte-identical to rhg_generate's for the same parameters.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
 #include "query_dev.h"
+#include "rhg_internal.h"
 
 namespace rhgk {
 using namespace rhgd;
@@ -364,3 +369,186 @@ void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *
 }
 
 }  // namespace rhgk
+
+// ---------------------------------------------------------------------------
+// Scratch layout of one request on this path (shared by the server's groups
+// and the allocation-free entry point below).
+// ---------------------------------------------------------------------------
+namespace rhgi {
+
+using rhgd::BITMAP_WORDS;
+
+SmallLayout small_layout_units(uint64_t n, int B, uint64_t unit_cap, bool fp32) {
+    SmallLayout L;
+    const uint64_t nb = (n + 63) / 64;
+    L.unit_cap = unit_cap;
+    L.win_cap = n * (uint64_t)B;
+    // slab j's bucket table has 2^bits_j + 1 <= n_j + 2 entries
+    L.btab_cap = n + 2ull * B + 8;
+    uint64_t b = 0;
+    b += 4 * align256(4 * n);                          // keys, vals, keys2, vals2
+    b += 2 * align256(8 * n) + 2 * align256(16 * n);   // th, sh, epm, hsc
+    if (fp32) b += align256(16 * n);                   // f32
+    b += align256(4 * L.btab_cap) + align256(8 * L.win_cap);
+    b += 2 * align256(8 * nb) + 2 * align256(8 * (nb + 1)) + align256(8 * nb * (uint64_t)(B + 1));
+    b += 2 * align256(4 * L.unit_cap) + align256(8 * (L.unit_cap + 1)) + align256(8 * L.unit_cap * BITMAP_WORDS);
+    L.bytes = b;
+    return L;
+}
+
+void small_fill_desc(rhgk::SmallDesc &D, const Plan &pl, const Request &rq, const SmallLayout &lay, char *base,
+                     unsigned long long *stats) {
+    std::memset(&D, 0, sizeof(D));
+    D.src.mode = rhgd::SRC_SEED;
+    D.src.n = pl.n;
+    D.src.seed = rq.seed;
+    D.src.alpha = rq.alpha;
+    D.src.R = rq.R;
+    D.src.sinh_half_aR = std::sinh(rq.alpha * rq.R / 2.0);
+    geo_static(pl, D.geo);
+    D.fp32 = pl.fp32 ? 1 : 0;
+    D.key_bits = key_bits_for(pl.B);
+    const uint64_t n = pl.n, nb = (n + 63) / 64;
+    char *p = base;
+    auto take = [&](uint64_t bytes) {
+        char *x = p;
+        p += align256(bytes);
+        return (void *)x;
+    };
+    D.keys = (uint32_t *)take(4 * n);
+    D.vals = (uint32_t *)take(4 * n);
+    D.keys2 = (uint32_t *)take(4 * n);
+    D.vals2 = (uint32_t *)take(4 * n);
+    D.th = (double *)take(8 * n);
+    D.sh = (double *)take(8 * n);
+    D.epm = (double2 *)take(16 * n);
+    D.hsc = (double2 *)take(16 * n);
+    D.f32 = pl.fp32 ? (float4 *)take(16 * n) : nullptr;
+    D.btab_cap = lay.btab_cap;
+    D.btab = (uint32_t *)take(4 * D.btab_cap);
+    D.win_cap = lay.win_cap;
+    D.win = (uint2 *)take(8 * D.win_cap);
+    D.bcand = (uint64_t *)take(8 * nb);
+    D.nunits = (uint64_t *)take(8 * nb);
+    D.boff = (uint64_t *)take(8 * (nb + 1));
+    D.uoff = (uint64_t *)take(8 * (nb + 1));
+    D.bsoff = (uint64_t *)take(8 * nb * (uint64_t)(pl.B + 1));
+    D.unit_cap = lay.unit_cap;
+    D.ubatch = (uint32_t *)take(4 * D.unit_cap);
+    D.uedges = (uint32_t *)take(4 * D.unit_cap);
+    D.ueoff = (uint64_t *)take(8 * (D.unit_cap + 1));
+    D.bits = (unsigned long long *)take(8 * D.unit_cap * BITMAP_WORDS);
+    D.stats = stats;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free generation (rhg_generate_noalloc): one request of at most
+// NOALLOC_N points on the one-launch path, with every work array in `scratch`,
+// a fixed device array of NOALLOC_BYTES that each device holds from the
+// library's load until the process ends.
+//
+// Layout of the scratch (offsets in bytes):
+//   0                  the request's descriptor (uploaded from pinned host memory)
+//   HDR_ZERO           pool_used, rechecks, disagreements: three words that
+//                      must start at zero, cleared by the same upload
+//   HDR_RESULT         the request's SmallResult
+//   HDR_BYTES ..       the request's arrays (small_layout_units with the
+//                      worst-case unit count of n points)
+//
+// In host code `scratch` names a host-side stand-in: the device address of
+// each device's copy is taken once per device with hipGetSymbolAddress
+// (noalloc_setup, from rhg_ctx_create with that device current) and only
+// that address is used.  Calls on one device share its array: calls that
+// overlap in time on one device race and must be serialised by the caller.
+// ---------------------------------------------------------------------------
+constexpr uint64_t NOALLOC_N = 8192;
+constexpr uint64_t NOALLOC_BYTES = 16ull << 20;
+constexpr uint64_t HDR_ZERO = align256(sizeof(rhgk::SmallDesc));
+constexpr uint64_t HDR_RESULT = HDR_ZERO + 256;
+constexpr uint64_t HDR_BYTES = 4096;
+constexpr uint64_t PIN_RESULT = 3072;  // the result's read-back place in the context's 4 KB pinned area
+static_assert(HDR_RESULT + sizeof(rhgk::SmallResult) <= HDR_BYTES, "scratch header");
+static_assert(HDR_ZERO + 3 * sizeof(unsigned long long) <= PIN_RESULT, "descriptor upload must not reach the result");
+static_assert(PIN_RESULT + sizeof(rhgk::SmallResult) <= 4096, "pinned area");
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Most work units a request of n points can have: a query's windows hold at
+// most n - 1 candidates in all (disjoint slabs; its own slab without
+// itself), so a 64-query batch has at most 64 (n - 1), in ceil(64 (n-1) / UNIT)
+// units.
+static uint64_t max_units(uint64_t n) {
+    const uint64_t nb = (n + 63) / 64;
+    return nb * ((64 * (n - 1) + rhgd::UNIT - 1) / rhgd::UNIT);
+}
+
+rhg_status noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return RHG_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return RHG_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return RHG_EDEVICE;
+    }
+    g_noalloc_ptr[device] = p;
+    return RHG_OK;
+}
+
+}  // namespace rhgi
+
+#define NOALLOC_HIP(expr)                                  \
+    do {                                                   \
+        const rhg_status _s = rhgi::hip_status(expr);      \
+        if (_s != RHG_OK) return _s;                       \
+    } while (0)
+
+extern "C" rhg_status rhg_generate_noalloc(rhg_ctx *ctx, const rhg_params *params, int32_t *dev_pairs,
+                                           uint64_t capacity_pairs, uint64_t *m) {
+    using namespace rhgi;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !m) return RHG_EINVAL;
+    if (c->shard_count != 1) return RHG_EINVAL;  // one whole graph per call
+    Request rq;
+    rhg_status s = request_from_params(params, rq);
+    if (s != RHG_OK) return s;
+    Plan pl;
+    s = describe(rq, pl);
+    if (s != RHG_OK) return s;
+    if (pl.n > NOALLOC_N) return RHG_ERANGE;
+    const SmallLayout lay = small_layout_units(pl.n, pl.B, max_units(pl.n), pl.fp32);
+    if (HDR_BYTES + lay.bytes > NOALLOC_BYTES) return RHG_ERANGE;  // (not reached for n <= NOALLOC_N, B <= 32)
+    if (!dev_pairs && capacity_pairs) return RHG_EINVAL;
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (c->device >= 0 && c->device < NOALLOC_MAX_DEVICES) base = (char *)g_noalloc_ptr[c->device];
+    }
+    if (!base || !c->pinned) return RHG_EDEVICE;
+    NOALLOC_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();
+    const hipStream_t st = c->stream;
+    // descriptor and the three zeroed words, staged in the context's pinned
+    // area and uploaded with one copy
+    char *pin = (char *)c->pinned;
+    unsigned long long *zero_dev = (unsigned long long *)(base + HDR_ZERO);
+    rhgk::SmallDesc &D = *(rhgk::SmallDesc *)pin;
+    small_fill_desc(D, pl, rq, lay, base + HDR_BYTES, zero_dev + 1);
+    std::memset(pin + HDR_ZERO, 0, 3 * sizeof(unsigned long long));
+    NOALLOC_HIP(hipMemcpyAsync(base, pin, HDR_ZERO + 3 * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+    rhgk::SmallResult *res_dev = (rhgk::SmallResult *)(base + HDR_RESULT);
+    rhgk::small_group((const rhgk::SmallDesc *)base, res_dev, 1, (int2 *)dev_pairs, zero_dev, capacity_pairs, st);
+    NOALLOC_HIP(hipGetLastError());
+    rhgk::SmallResult *res = (rhgk::SmallResult *)(pin + PIN_RESULT);
+    NOALLOC_HIP(hipMemcpyAsync(res, res_dev, sizeof(rhgk::SmallResult), hipMemcpyDeviceToHost, st));
+    NOALLOC_HIP(hipStreamSynchronize(st));
+    *m = res->m;
+    if (res->status == 2) return RHG_ETRUNC;  // m pairs do not fit: nothing written
+    if (res->status != 0) return RHG_EDEVICE;  // scratch sized for the worst case: not expected
+    return RHG_OK;
+}

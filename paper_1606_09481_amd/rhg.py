@@ -101,6 +101,7 @@ def load(path: Optional[str] = None):
         "rhg_csr_from_pairs": (i32, [vp, u64, vp, u64, vp, vp]),
         "rhg_count": (i32, [vp, P(rhg_params), P(vp), P(u64)]),
         "rhg_emit": (i32, [vp, vp, vp, u64]),
+        "rhg_generate_noalloc": (i32, [vp, P(rhg_params), vp, u64, P(u64)]),
         "rhg_graph_num_edges": (i32, [vp, P(u64)]),
         "rhg_graph_num_points": (i32, [vp, P(u64)]),
         "rhg_graph_radius": (i32, [vp, P(d)]),
@@ -281,6 +282,19 @@ def rhg_count(ctx, p: rhg_params) -> Tuple[ctypes.c_void_p, int]:
 def rhg_emit(ctx, plan, dev_pairs, capacity_pairs: int):
     """dev_pairs: a torch int32 tensor on the GPU (>= 2*m elements) or a device address."""
     _check(load().rhg_emit(ctx, plan, _ptr(dev_pairs), int(capacity_pairs)), "rhg_emit")
+
+
+def rhg_generate_noalloc(ctx, p: rhg_params, dev_pairs, capacity_pairs: int) -> int:
+    """One seeded request (n <= 8192) into dev_pairs (torch int32 tensor on the
+    GPU, or a device address) without any device allocation; returns m.
+    Raises RhgError(RHG_ETRUNC) when m > capacity_pairs (its .m holds m)."""
+    m = ctypes.c_uint64()
+    s = load().rhg_generate_noalloc(ctx, ctypes.byref(p), _ptr(dev_pairs), int(capacity_pairs), ctypes.byref(m))
+    if s != RHG_OK:
+        e = RhgError(s, "rhg_generate_noalloc")
+        e.m = m.value
+        raise e
+    return m.value
 
 
 # ---- graph handle ------------------------------------------------------------------
