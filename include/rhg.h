@@ -170,10 +170,11 @@ rhg_status rhg_band_boundaries(double R, uint32_t num_bands, double band_ratio, 
  * edges stay in device memory until rhg_graph_free. */
 rhg_status rhg_generate(rhg_ctx *ctx, const rhg_params *params, rhg_graph **out);
 
-/* Same for caller coordinates: theta[n] in [0, 2pi] (2pi meaning fl(2*pi)),
+/* Same for caller coordinates (the polar coordinates of Sec. II; Algorithm 1
+ * from its slab step on): theta[n] in [0, 2pi] (2pi meaning fl(2*pi)),
  * r[n] in [0, R], 0 < R <= 354, FP64, host or device memory (coords_on_device
  * = 0/1; device arrays are only read).  Edges use the positions in these
- * arrays. */
+ * arrays: {u, v} iff dist_H(u, v) < R by Eq. 3. */
 rhg_status rhg_generate_from_coords(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r, double R,
                                     rhg_precision precision, int coords_on_device, rhg_graph **out);
 
@@ -251,8 +252,11 @@ rhg_status rhg_update_after_move(rhg_ctx *ctx, uint64_t n, const double *theta, 
 rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t *pairs, uint64_t m, uint64_t *row_ptr,
                               int32_t *col);
 
-/* Two-phase form for caller-owned output (e.g. a PyTorch tensor):
- * rhg_count plans and counts (m), rhg_emit writes the m pairs into
+/* Two-phase form for caller-owned output (e.g. a PyTorch tensor) of
+ * rhg_generate (Algorithm 1, Sec. III-B): rhg_count samples the points,
+ * sorts the slabs, plans the getMinMaxPhi windows and decides every
+ * candidate pair by Eq. 3 (m = the number of edges); rhg_emit adds the edges
+ * (the decisions replayed, not re-tested), writing the m pairs into
  * dev_pairs (device, >= 2*m int32, capacity_pairs in pairs; RHG_ETRUNC if
  * smaller, nothing written).  *plan is a graph handle without edges; free it
  * with rhg_graph_free.  rhg_emit may be called once per plan. */
