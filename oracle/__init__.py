@@ -83,6 +83,18 @@ def lib():
         L.orc_move.argtypes = [u64, d, d, vp, vp, vp, vp]
         L.orc_free.restype = None
         L.orc_free.argtypes = [vp]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.orc_pair_uniform.restype = d
+        L.orc_pair_uniform.argtypes = [u64, i64, i64]
+        L.orc_fd_prob.restype = d
+        L.orc_fd_prob.argtypes = [d, d, d]
+        L.orc_soft_is_edge.restype = i32
+        L.orc_soft_is_edge.argtypes = [vp, vp, vp, vp, vp, i64, i64, d, d, u64]
+        L.orc_soft_brute.restype = i64
+        L.orc_soft_brute.argtypes = [i64, vp, vp, vp, vp, vp, d, d, u64, PP, PP, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_soft_band_sweep.restype = i64
+        L.orc_soft_band_sweep.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, d, d, u64, i32, d, i32, PP, PP,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
     return _lib
 
@@ -292,3 +304,72 @@ def move(theta: np.ndarray, r: np.ndarray, tau_phi: np.ndarray, tau_r: np.ndarra
     lib().orc_move(len(th), float(alpha), float(R), _ptr(th), _ptr(rr), _ptr(tp), _ptr(tr))
     return th, rr, tr
 
+
+
+# --------------------------------------------------------------------------
+# General model at temperature T > 0 (Sec. II, Eq. 2)
+# --------------------------------------------------------------------------
+def pair_uniform(seed: int, lo: int, hi: int) -> float:
+    """The uniform in (0, 1] that decides pair {lo, hi} (lo < hi)."""
+    return lib().orc_pair_uniform(int(seed) & (2**64 - 1), int(lo), int(hi))
+
+
+def fd_prob(V: float, R: float, T: float) -> float:
+    """Eq. 2: 1 / (exp((acosh V - R) / (2T)) + 1) (acosh V taken as 0 for V <= 1)."""
+    return lib().orc_fd_prob(float(V), float(R), float(T))
+
+
+def soft_is_edge(tab: np.ndarray, u: int, v: int, R: float, T: float, seed: int) -> bool:
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    return bool(lib().orc_soft_is_edge(_ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]), _ptr(tab[4]),
+                                       int(u), int(v), float(R), float(T), int(seed) & (2**64 - 1)))
+
+
+def _take_soft(ptr, m, tptr, nt):
+    if m == EDOMAIN:
+        for q in (ptr, tptr):
+            if q.value:
+                lib().orc_free(q)
+        raise ValueError("outside the oracle's domain (0 < T < 1, R in (0, 354])")
+    e = _take(ptr, m)
+    ties = _take(tptr, int(nt.value)) if m >= 0 else None
+    return e, ties
+
+
+def soft_brute(tab: np.ndarray, R: float, T: float, seed: int, with_ties: bool = False):
+    """All pairs i < j, each an edge iff its uniform is below Eq. 2's
+    probability; (m, 2) int32 sorted.  with_ties: also the near ties (pairs
+    whose uniform lies within the rounding band of the probability)."""
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    p, tp, nt = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+    m = lib().orc_soft_brute(tab.shape[1], _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]), _ptr(tab[3]), _ptr(tab[4]),
+                             float(R), float(T), int(seed) & (2**64 - 1), ctypes.byref(p), ctypes.byref(tp),
+                             ctypes.byref(nt))
+    e, ties = _take_soft(p, m, tp, nt)
+    return (e, ties) if with_ties else e
+
+
+def soft_band_sweep(theta: np.ndarray, r: np.ndarray, tab: np.ndarray, R: float, T: float, seed: int,
+                    B: Optional[int] = None, p: float = 0.9, threads: int = 0, with_ties: bool = False,
+                    with_candidates: bool = False):
+    """Band sweep of the general model (windows for R + 80 T); edges in block order."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    n = len(theta)
+    if B is None:
+        B = default_bands(n)
+    if threads <= 0:
+        threads = default_threads()
+    ptr, tp, nt, cand = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_uint64()
+    m = lib().orc_soft_band_sweep(n, _ptr(theta), _ptr(r), _ptr(tab[0]), _ptr(tab[1]), _ptr(tab[2]),
+                                  _ptr(tab[3]), _ptr(tab[4]), float(R), float(T), int(seed) & (2**64 - 1), int(B),
+                                  float(p), int(threads), ctypes.byref(ptr), ctypes.byref(tp), ctypes.byref(nt),
+                                  ctypes.byref(cand))
+    e, ties = _take_soft(ptr, m, tp, nt)
+    out = [e]
+    if with_ties:
+        out.append(ties)
+    if with_candidates:
+        out.append(int(cand.value))
+    return out[0] if len(out) == 1 else tuple(out)

@@ -37,6 +37,13 @@
  *   orc_move                             -- one movement step of the dynamic
  *        model (Sec. III-C: rotation, Algorithm 2's radial step, reflection
  *        at 0 and R), in the reading under which Theorem 1 holds (below).
+ *   orc_pair_uniform / orc_fd_prob / orc_soft_brute / orc_soft_band_sweep
+ *                                        -- the general model at temperature
+ *        T > 0 (Sec. II, Eq. 2): each pair an edge with probability
+ *        1/(exp((x - R)/(2T)) + 1) of its distance x, decided by one uniform
+ *        per unordered pair (a reading: the paper gives no algorithm for
+ *        T > 0); all pairs, and the band sweep with the radius enlarged to
+ *        where that probability falls below the smallest uniform.
  *
  * Readings where the paper is silent or ambiguous (all listed in the design
  * notes of the repository): strict "< R"; half-open slabs with r = R in the
@@ -638,3 +645,252 @@ void orc_move(uint64_t n, double alpha, double R, double *theta, double *r, cons
     }
 }
 
+
+/* ------------------------------------------------------------------------- */
+/* General model, temperature T > 0 (Sec. II, Eq. 2).                         */
+/*                                                                            */
+/* Eq. 2 gives pair {u, v} at distance x the edge probability                 */
+/*   f(x) = 1 / (exp((x - R) / (2 T)) + 1).                                   */
+/* The paper gives no algorithm for T > 0; the reading used here decides      */
+/* each unordered pair {lo, hi} (lo < hi, original indices) once, with its    */
+/* own uniform U in (0, 1]: edge iff U < f(x).  U comes from the points'      */
+/* SplitMix64 generator (same seed) at output 2^62 + lo 2^31 + hi, far from   */
+/* the outputs 0 .. 2n - 1 the points use (n < 2^31), mapped to               */
+/* ((z >> 11) + 1) 2^-53.  x = acosh(V) with V the cosh distance of Eq. 3 as  */
+/* evaluated above (x = 0 for V <= 1: rounding can put coincident points a    */
+/* hair below 1), y = (x - R) / (2 T), f = 1 / (1 + exp(y)), all FP64.        */
+/* ------------------------------------------------------------------------- */
+double orc_pair_uniform(uint64_t seed, int64_t lo, int64_t hi) {
+    uint64_t k = ((uint64_t)1 << 62) + ((uint64_t)lo << 31) + (uint64_t)hi;
+    uint64_t z = orc_splitmix64(seed, k);
+    return (double)((z >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+
+double orc_fd_prob(double V, double R, double T) {
+    double x = V > 1.0 ? acosh(V) : 0.0;
+    double y = (x - R) / (2.0 * T);
+    return 1.0 / (1.0 + exp(y));
+}
+
+/* Relative width of the band around f within which two correct FP64
+ * evaluations of f from the same V may fall on different sides of U: acosh
+ * within 2 ulp on either side (4 ulp of x apart), scaled by 1/(2T) in y, plus
+ * a few ulp for exp and the division; taken 4 times over. */
+static double orc_tie_width(double V, double T) {
+    double x = V > 1.0 ? acosh(V) : 1.0;
+    if (x < 1.0) x = 1.0;
+    double ulp = nextafter(x, INFINITY) - x;
+    return 16.0 * ulp / (2.0 * T) + 0x1p-45;
+}
+
+static int orc_T_ok(double R, double T) {
+    return T > 0.0 && T < 1.0 && isfinite(T) && R > 0.0 && R <= ORC_R_MAX;
+}
+
+int orc_soft_is_edge(const double *ep, const double *em, const double *sh, const double *hs, const double *hc,
+                     int64_t u, int64_t v, double R, double T, uint64_t seed) {
+    if (u == v) return 0;
+    orc_tab t = {ep, em, sh, hs, hc};
+    int64_t lo = u < v ? u : v, hi = u < v ? v : u;
+    return orc_pair_uniform(seed, lo, hi) < orc_fd_prob(orc_V(&t, u, v), R, T);
+}
+
+/* Edge decision of one pair, and whether it is a near tie (U within the
+ * rounding band of f). */
+static int orc_soft_decide(const orc_tab *t, int64_t u, int64_t v, double R, double T, uint64_t seed, int *tie) {
+    int64_t lo = u < v ? u : v, hi = u < v ? v : u;
+    double V = orc_V(t, u, v);
+    double U = orc_pair_uniform(seed, lo, hi);
+    double f = orc_fd_prob(V, R, T);
+    *tie = fabs(U - f) <= orc_tie_width(V, T) * f;
+    return U < f;
+}
+
+/* All pairs i < j (the plain definition).  Near ties go to *ties (may be
+ * NULL).  Returns m, ORC_EDOMAIN, or -1 on allocation failure. */
+int64_t orc_soft_brute(int64_t n, const double *ep, const double *em, const double *sh, const double *hs,
+                       const double *hc, double R, double T, uint64_t seed, int32_t **out, int32_t **ties,
+                       int64_t *nties) {
+    *out = NULL;
+    if (ties) *ties = NULL;
+    if (nties) *nties = 0;
+    if (!orc_T_ok(R, T)) return ORC_EDOMAIN;
+    orc_tab t = {ep, em, sh, hs, hc};
+    orc_buf b = {0}, tb = {0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            int tie = 0;
+            if (orc_soft_decide(&t, i, j, R, T, seed, &tie)) orc_push(&b, i, j);
+            if (tie) orc_push(&tb, i, j);
+        }
+    if (b.oom || tb.oom) { free(b.p); free(tb.p); return -1; }
+    *out = b.p;
+    if (ties) *ties = tb.p; else free(tb.p);
+    if (nties) *nties = tb.m;
+    return b.m;
+}
+
+/* Band sweep of the general model: Algorithm 1's slabs, angle sort and
+ * getMinMaxPhi windows, for the enlarged radius Rc = R + 80 T (beyond it
+ * y > 40 and f < e^-40 < 2^-53 <= U: no pair there can be an edge), then the
+ * decision above for every candidate.  Same-slab pairs once, by index.  As
+ * orc_band_sweep, plus the near ties in *ties. */
+typedef struct {
+    int64_t n, block, nblocks;
+    const double *theta, *r;
+    orc_tab tab;
+    double R, T, Kc;
+    uint64_t seed;
+    int B;
+    const double *c;
+    const int *band;
+    const orc_pt *sorted;
+    const int64_t *band_off;
+    volatile int64_t next;
+    orc_buf *bufs, *tbufs;
+    uint64_t *cands;
+} orc_soft_ctx;
+
+static void orc_soft_range(orc_soft_ctx *X, int64_t v, int j, int64_t a, int64_t e, orc_buf *b, orc_buf *tb,
+                           uint64_t *cand) {
+    for (int64_t k = a; k < e; ++k) {
+        int64_t w = X->sorted[k].id;
+        if (w == v) continue;
+        if (j == X->band[v] && w < v) continue;
+        ++*cand;
+        int tie = 0;
+        if (orc_soft_decide(&X->tab, v, w, X->R, X->T, X->seed, &tie)) orc_push(b, v, w);
+        if (tie) orc_push(tb, v, w);
+    }
+}
+
+static void *orc_soft_worker(void *arg) {
+    orc_soft_ctx *X = (orc_soft_ctx *)arg;
+    for (;;) {
+        int64_t blk = __sync_fetch_and_add(&X->next, 1);
+        if (blk >= X->nblocks) break;
+        orc_buf *b = &X->bufs[blk], *tb = &X->tbufs[blk];
+        uint64_t cand = 0;
+        int64_t v0 = blk * X->block, v1 = v0 + X->block < X->n ? v0 + X->block : X->n;
+        for (int64_t v = v0; v < v1; ++v) {
+            double tv = X->theta[v], rv = X->r[v];
+            for (int j = X->band[v]; j < X->B; ++j) {
+                int64_t bs = X->band_off[j], be = X->band_off[j + 1];
+                if (be == bs) continue;
+                double delta;
+                int whole = (j == 0) ? 1 : orc_window(rv, X->c[j], X->Kc, &delta);
+                if (whole) {
+                    orc_soft_range(X, v, j, bs, be, b, tb, &cand);
+                    continue;
+                }
+                double lo = tv - delta, hi = tv + delta;
+                if (lo < 0.0) {
+                    orc_soft_range(X, v, j, bs, orc_upper(X->sorted, bs, be, hi), b, tb, &cand);
+                    orc_soft_range(X, v, j, orc_lower(X->sorted, bs, be, lo + ORC_TWO_PI), be, b, tb, &cand);
+                } else if (hi > ORC_TWO_PI) {
+                    orc_soft_range(X, v, j, orc_lower(X->sorted, bs, be, lo), be, b, tb, &cand);
+                    orc_soft_range(X, v, j, bs, orc_upper(X->sorted, bs, be, hi - ORC_TWO_PI), b, tb, &cand);
+                } else {
+                    orc_soft_range(X, v, j, orc_lower(X->sorted, bs, be, lo), orc_upper(X->sorted, bs, be, hi), b,
+                                   tb, &cand);
+                }
+            }
+        }
+        X->cands[blk] = cand;
+    }
+    return NULL;
+}
+
+static int32_t *orc_concat(orc_buf *bufs, int64_t nb, int64_t *m_out) {
+    int64_t m = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+        if (bufs[k].oom) return NULL;
+        m += bufs[k].m;
+    }
+    int32_t *all = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * 2 * sizeof(int32_t));
+    if (!all) return NULL;
+    int64_t at = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+        if (bufs[k].m) memcpy(all + 2 * at, bufs[k].p, (size_t)bufs[k].m * 2 * sizeof(int32_t));
+        at += bufs[k].m;
+    }
+    *m_out = m;
+    return all;
+}
+
+int64_t orc_soft_band_sweep(int64_t n, const double *theta, const double *r, const double *ep, const double *em,
+                            const double *sh, const double *hs, const double *hc, double R, double T, uint64_t seed,
+                            int B, double p, int nthreads, int32_t **out, int32_t **ties, int64_t *nties,
+                            uint64_t *candidates_out) {
+    *out = NULL;
+    *ties = NULL;
+    *nties = 0;
+    if (B < 1 || n < 0) return -1;
+    if (!orc_T_ok(R, T)) return ORC_EDOMAIN;
+    double *c = (double *)malloc((size_t)(B + 1) * sizeof(double));
+    int *band = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    int64_t *band_off = (int64_t *)calloc((size_t)B + 1, sizeof(int64_t));
+    orc_pt *sorted = (orc_pt *)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_pt));
+    int64_t *fill = (int64_t *)calloc((size_t)B + 1, sizeof(int64_t));
+    if (!c || !band || !band_off || !sorted || !fill) {
+        free(c); free(band); free(band_off); free(sorted); free(fill);
+        return -1;
+    }
+    /* slabs of the disk of radius R (the points' disk); windows for Rc */
+    orc_boundaries(R, B, p, c);
+    for (int64_t v = 0; v < n; ++v) {
+        band[v] = orc_band_of(r[v], c, B);
+        band_off[band[v] + 1]++;
+    }
+    for (int j = 0; j < B; ++j) band_off[j + 1] += band_off[j];
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t k = band_off[band[v]] + fill[band[v]]++;
+        sorted[k].theta = theta[v];
+        sorted[k].id = v;
+    }
+    for (int j = 0; j < B; ++j)
+        qsort(sorted + band_off[j], (size_t)(band_off[j + 1] - band_off[j]), sizeof(orc_pt), orc_cmp_pt);
+    orc_soft_ctx X;
+    memset(&X, 0, sizeof X);
+    X.n = n; X.block = 1024; X.nblocks = (n + X.block - 1) / X.block;
+    X.theta = theta; X.r = r;
+    X.tab.ep = ep; X.tab.em = em; X.tab.sh = sh; X.tab.hs = hs; X.tab.hc = hc;
+    X.R = R; X.T = T; X.seed = seed; X.Kc = cosh(R + 80.0 * T);
+    X.B = B; X.c = c; X.band = band; X.sorted = sorted; X.band_off = band_off;
+    X.next = 0;
+    int64_t nbk = X.nblocks > 0 ? X.nblocks : 1;
+    X.bufs = (orc_buf *)calloc((size_t)nbk, sizeof(orc_buf));
+    X.tbufs = (orc_buf *)calloc((size_t)nbk, sizeof(orc_buf));
+    X.cands = (uint64_t *)calloc((size_t)nbk, sizeof(uint64_t));
+    int64_t m = -1;
+    if (X.bufs && X.tbufs && X.cands) {
+        if (nthreads < 1) nthreads = 1;
+        pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+        int started = 0;
+        if (th) {
+            for (int t = 0; t < nthreads; ++t)
+                if (pthread_create(&th[t], NULL, orc_soft_worker, &X) == 0) ++started;
+            for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+            free(th);
+        }
+        if (started == 0) orc_soft_worker(&X);
+        int64_t mt = 0;
+        int32_t *all = orc_concat(X.bufs, X.nblocks, &m);
+        int32_t *tall = all ? orc_concat(X.tbufs, X.nblocks, &mt) : NULL;
+        if (!all || !tall) {
+            free(all); free(tall);
+            m = -1;
+        } else {
+            *out = all;
+            *ties = tall;
+            *nties = mt;
+            uint64_t cand = 0;
+            for (int64_t k = 0; k < X.nblocks; ++k) cand += X.cands[k];
+            if (candidates_out) *candidates_out = cand;
+        }
+        for (int64_t k = 0; k < X.nblocks; ++k) { free(X.bufs[k].p); free(X.tbufs[k].p); }
+    }
+    free(X.bufs); free(X.tbufs); free(X.cands);
+    free(c); free(band); free(band_off); free(sorted); free(fill);
+    return m;
+}
