@@ -112,6 +112,8 @@ typedef struct {
     double ms[8];
     uint64_t bytes_moved;
     double count_kernel_ms;
+    uint64_t literal_undecided; /* RHG_OPT_LITERAL_ABLATION: candidates Eq. 3 as printed, in FP32, leaves undecided */
+    uint64_t literal_wrong;     /* RHG_OPT_LITERAL_ABLATION: its plain FP32 decisions that differ from FP64 */
 } rhg_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -144,8 +146,20 @@ rhg_status rhg_ctx_set_allocator(rhg_ctx *ctx, void *(*alloc)(size_t, void *), v
  *   Each edge is found by exactly one query, so the S shards' edge lists are
  *   disjoint and together are the whole graph.  rhg_stats.edges and
  *   .candidates then count the shard only.  A generation with k >= S returns
- *   RHG_EINVAL.  The serving path ignores these options. */
-typedef enum { RHG_OPT_FP32_EXHAUSTIVE = 1, RHG_OPT_SHARD_COUNT = 2, RHG_OPT_SHARD_INDEX = 3 } rhg_option;
+ *   RHG_EINVAL.  The serving path ignores these options.
+ *   RHG_OPT_LITERAL_ABLATION (value 0/1): in RHG_FP32_RECHECK count passes
+ *   also decide every candidate by Eq. 3 as printed (cosh r_u cosh r_v -
+ *   sinh r_u sinh r_v cos(theta_u - theta_v)) in FP32 and count into
+ *   rhg_stats.literal_undecided the candidates within its sound rounding
+ *   margin 8 u32 (A + S) of cosh R (A, S the two products) and into
+ *   .literal_wrong its plain FP32 decisions that differ from the FP64 test
+ *   (the edges themselves stay those of the FP64 test; slower). */
+typedef enum {
+    RHG_OPT_FP32_EXHAUSTIVE = 1,
+    RHG_OPT_SHARD_COUNT = 2,
+    RHG_OPT_SHARD_INDEX = 3,
+    RHG_OPT_LITERAL_ABLATION = 4
+} rhg_option;
 rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value);
 
 /* Release the context and its work buffers (graphs stay valid). */
@@ -262,6 +276,37 @@ rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t *pairs, ui
  * with rhg_graph_free.  rhg_emit may be called once per plan. */
 rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_graph **plan, uint64_t *m);
 rhg_status rhg_emit(rhg_ctx *ctx, rhg_graph *plan, int32_t *dev_pairs, uint64_t capacity_pairs);
+
+/* ---- general model, temperature T > 0 (Sec. II, Eq. 2) -------------------
+ * Each pair {u, v} at hyperbolic distance x (Eq. 3) is an edge with
+ * probability f(x) = 1 / (exp((x - R) / (2T)) + 1).  The paper gives no
+ * algorithm for T > 0; this library decides every unordered pair {lo, hi}
+ * (lo < hi, original indices) once with its own uniform
+ *   U = ((z >> 11) + 1) 2^-53 in (0, 1],  z = SplitMix64 output number
+ *   2^62 + lo 2^31 + hi of the generator seeded with `seed`
+ * (the points' outputs are 0 .. 2n - 1), edge iff U < f(x), evaluated in FP64
+ * in this order: V the cosh distance as for the threshold model,
+ * x = acosh(V) (0 for V <= 1), y = (x - R) / (2T), f = 1 / (1 + exp(y)).  The
+ * band query of Algorithm 1 runs for the enlarged radius Rc = R + 74 T:
+ * beyond it f < 2^-53 <= U, so no pair there can be an edge, and the edge set
+ * is that of the all-pairs rule.  The work grows about like e^{37 T} times
+ * the threshold model's: meant for small T (the limit T -> 0 is the
+ * threshold graph).  Same output, ownership and error conventions as the
+ * threshold calls; only RHG_FP64.  RHG_EINVAL besides: T outside (0, 1),
+ * RHG_FP32_RECHECK, or R + 74 T > 354. */
+
+/* Seeded points (Eq. 1) from params->seed, which also seeds the pairs'
+ * uniforms.  With R <= 0, R = getTargetRadius(n, alpha, kbar sin(pi T) /
+ * (pi T)): the expected degree at temperature T is about pi T / sin(pi T)
+ * times that of the threshold model with the same R. */
+rhg_status rhg_generate_soft(rhg_ctx *ctx, const rhg_params *params, double T, rhg_graph **out);
+/* The same as a count-only plan, emitted with rhg_emit into caller memory. */
+rhg_status rhg_count_soft(rhg_ctx *ctx, const rhg_params *params, double T, rhg_graph **plan, uint64_t *m);
+/* Caller points and table (layout and memory kinds as rhg_generate_from_table),
+ * disk radius R, temperature T, and the seed of the pairs' uniforms. */
+rhg_status rhg_generate_soft_from_table(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
+                                        const double *table5xn, double R, double T, uint64_t seed, int on_device,
+                                        rhg_graph **out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): rhg_count

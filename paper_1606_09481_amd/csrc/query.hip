@@ -148,6 +148,29 @@ __global__ __launch_bounds__(256, 7) void k_count(QueryArgs A) {
     count_unit<FP32, WIDE, FULL>(A, unit, k, lane, sm[w]);
 }
 
+// The general model's count: the same walk with the probabilistic decision;
+// its transcendentals need more registers than 7 wavefronts per SIMD leave.
+template <bool WIDE>
+__global__ __launch_bounds__(256, 4) void k_count_soft(QueryArgs A) {
+    __shared__ CountSmem<0, false, true> sm[4];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    uint64_t k;
+    const uint64_t unit = exec_unit(A, w, k);
+    if (unit == ~0ull) return;
+    count_unit<0, WIDE, false, true>(A, unit, k, lane, sm[w]);
+}
+
+// The FP32 form with the literal-Eq. 3 ablation counters (a measurement, not a timed path).
+template <bool WIDE>
+__global__ __launch_bounds__(256, 4) void k_count_ablation(QueryArgs A) {
+    __shared__ CountSmem<1> sm[4];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    uint64_t k;
+    const uint64_t unit = exec_unit(A, w, k);
+    if (unit == ~0ull) return;
+    count_unit<1, WIDE, false, false, true>(A, unit, k, lane, sm[w]);
+}
+
 template <bool WIDE, bool FULL>
 __global__ __launch_bounds__(256) void k_emit(QueryArgs A) {
     __shared__ EmitSmem sm[4];
@@ -169,6 +192,18 @@ static void launch_count(const QueryArgs &a, hipStream_t st) {
 void query_count(const QueryArgs &a, int fp32, hipStream_t st) {
     if (!a.n_units) return;
     const bool full = a.geo.moved != nullptr;
+    if (a.geo.t2 > 0.0) {  // general model: FP64, no update mode
+        const dim3 grid(exec_blocks(a.n_units)), block(256);
+        if (a.geo.n >= (1u << 28)) hipLaunchKernelGGL((k_count_soft<true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_count_soft<false>), grid, block, 0, st, a);
+        return;
+    }
+    if (fp32 && a.exhaustive == 2 && !full) {  // literal-Eq. 3 ablation
+        const dim3 grid(exec_blocks(a.n_units)), block(256);
+        if (a.geo.n >= (1u << 28)) hipLaunchKernelGGL((k_count_ablation<true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_count_ablation<false>), grid, block, 0, st, a);
+        return;
+    }
     if (fp32) {
         if (full) launch_count<1, true>(a, st);
         else launch_count<1, false>(a, st);

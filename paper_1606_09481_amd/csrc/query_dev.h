@@ -192,6 +192,7 @@ struct Cand {
     double2 ew;  // (exp r_w, exp -r_w)        FP64 form
     double sh;   // sinh r_w                   FP64 form
     float4 f;    // FP32 shadows               FP32 form
+    uint32_t wi; // original index             general model (T > 0)
 };
 
 // Element i of a table column.  Unless WIDE, the byte offset is formed in 32
@@ -203,9 +204,10 @@ __device__ __forceinline__ T ld(const T *base, uint32_t i) {
     return *(const T *)((const char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
 }
 
-template <int FP32, bool WIDE>
+template <int FP32, bool WIDE, bool SOFT = false>
 __device__ __forceinline__ void load_cand(const Geo &g, uint32_t p, Cand &c) {
     c.hw = ld<WIDE>(g.hsc, p);
+    if (SOFT) c.wi = ld<WIDE>(g.idx, p);
     if (!FP32) {
         c.ew = ld<WIDE>(g.epm, p);
         c.sh = ld<WIDE>(g.sh, p);
@@ -216,7 +218,13 @@ __device__ __forceinline__ void load_cand(const Geo &g, uint32_t p, Cand &c) {
 
 // Returns bit 0 = edge, bit 1 = re-decided in FP64, bit 2 = FP32 decision
 // differed from FP64 (exhaustive self-check only).
-template <int FP32>
+// ABL (FP32 form, an ablation measurement): every candidate is also decided
+// by Eq. 3 as printed, cosh r_u cosh r_w - sinh r_u sinh r_w cos(theta_u -
+// theta_w), in FP32 from the FP32 shadows (cos and sin of the angles from the
+// half-angle table, rounded once): bit 3 = within the sound FP32 margin
+// 8 u32 (A + S) of cosh R (A, S the two products: such a pair would need an
+// FP64 recheck), bit 4 = its plain FP32 decision differs from the FP64 one.
+template <int FP32, bool ABL = false>
 __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const Cand &c, uint32_t p, int exhaustive) {
     const double d = q.hs * c.hw.y - q.hc * c.hw.x;
     if (!FP32) {
@@ -230,16 +238,51 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
         const float v32 = a32 + b32;
         const bool sure_in = v32 <= g.klo32, sure_out = v32 >= g.khi32;
         if (sure_in || sure_out) {
-            if (!exhaustive) return sure_in ? 1u : 0u;
+            if (!exhaustive && !ABL) return sure_in ? 1u : 0u;
         }
         const double2 e = g.epm[p];
         const double a = q.hep * e.y + q.hem * e.x;
         const double b = (q.sh2 * g.sh[p]) * (d * d);
         const uint32_t e64 = (a + b) < g.K ? 1u : 0u;
-        if (!(sure_in || sure_out)) return e64 | 2u;
+        uint32_t abl = 0u;
+        if (ABL) {
+            const float chu = q.hep32 + q.hem32, shu = 0.5f * q.sh2_32;
+            const float chw = 0.5f * (c.f.x + c.f.y);
+            const float cu = (float)(q.hc * q.hc - q.hs * q.hs), su = (float)(2.0 * (q.hs * q.hc));
+            const float cw = (float)(c.hw.y * c.hw.y - c.hw.x * c.hw.x), sw = (float)(2.0 * (c.hw.x * c.hw.y));
+            const float A = chu * chw, S = shu * c.f.z;
+            const float C = cu * cw + su * sw;
+            const float V = A - S * C;
+            const float K32 = (float)g.K;
+            abl |= (fabsf(V - K32) <= 8.0f * 0x1p-24f * (A + S)) ? 8u : 0u;
+            abl |= ((V < K32 ? 1u : 0u) != e64) ? 16u : 0u;
+        }
+        if (!(sure_in || sure_out)) return e64 | 2u | abl;
         const uint32_t f32dec = sure_in ? 1u : 0u;
-        return f32dec | (f32dec != e64 ? 4u : 0u);
+        return f32dec | (f32dec != e64 ? 4u : 0u) | abl;
     }
+}
+
+// General model at temperature T > 0 (Sec. II, Eq. 2): the pair is an edge
+// iff its uniform U = k 2^-53 is below f = 1 / (1 + exp((x - R) / (2T))),
+// x = acosh(V) (0 for V <= 1, where rounding can put coincident points),
+// with V the canonical FP64 cosh distance above, in this order of FP64
+// operations.  The windows and the first test belong to the enlarged radius
+// Rc (K = cosh Rc): at or beyond it f < 2^-53 <= U.  Before any
+// transcendental, U in [2^-(j+1), 2^-j) (j from the leading zeros of k)
+// needs f > 2^-(j+1), which needs V < lev[j+1] (with a margin far above the
+// rounding of f); most candidates stop there, so exp and acosh run for few.
+__device__ __forceinline__ uint32_t soft_test(const Geo &g, double V, uint32_t qi, uint32_t wi) {
+    if (!(V < g.K)) return 0u;
+    const uint32_t lo = qi < wi ? qi : wi, hi = qi < wi ? wi : qi;
+    const uint64_t k = pair_k(g.pseed, lo, hi);
+    const int j = __clzll((long long)k) - 11;  // U in [2^-(j+1), 2^-j); j = -1 for U = 1
+    if (j < 0 || !(V < g.lev[j + 1])) return 0u;
+    const double U = (double)k * 0x1p-53;
+    const double x = V > 1.0 ? acosh(V) : 0.0;
+    const double y = (x - g.R) / g.t2;
+    const double f = 1.0 / (1.0 + exp(y));
+    return U < f ? 1u : 0u;
 }
 
 // Per-unit setup shared by the count and emit passes: the unit's batch and
@@ -473,7 +516,7 @@ __device__ __forceinline__ uint32_t position_pb(uint32_t pb, uint32_t t, uint32_
 // Per-wavefront LDS of the count pass.
 // (FP32 operands only in the filter form, to keep the FP64 form's LDS, and
 // with it the workgroups per CU, down.)
-template <int FP32, bool FULL = false>
+template <int FP32, bool FULL = false, bool SOFT = false>
 struct CountSmem {
     uint32_t pb[64];    // per rank: start position - flattened offset
     uint8_t flag[64 * VT_COUNT];
@@ -482,6 +525,7 @@ struct CountSmem {
     unsigned long long bits[BITW];
     uint2 wpre[SEG_PRE][64];
     uint32_t qpos[FULL ? 64 : 1];  // per rank: the query's sorted position (update mode)
+    uint32_t qi[SOFT ? 64 : 1];    // per rank: the query's original index (general model)
 };
 
 // Ranks and positions of one count step (VT x 64 candidates from t0): the
@@ -507,13 +551,16 @@ __device__ __forceinline__ void count_positions(uint8_t *flags, const uint32_t *
 // FULL: update mode (Geo::moved): a candidate that passes the distance test
 // is an edge unless it is the query itself, or a moved point that comes
 // before the query in sorted order (that pair is the other query's).
-template <int FP32, bool WIDE, bool FULL = false>
+// SOFT: the general model (FP64 only), each candidate decided by soft_test.
+// ABL: the FP32 form with the literal-Eq. 3 ablation counters (edge_test).
+template <int FP32, bool WIDE, bool FULL = false, bool SOFT = false, bool ABL = false>
 __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane,
-                                           CountSmem<FP32, FULL> &S) {
+                                           CountSmem<FP32, FULL, SOFT> &S) {
     constexpr int VT = VT_COUNT;
     const Geo &g = A.geo;
     const UnitSetup u = unit_setup<FULL>(A, unit, lane);
     Qv mine{};
+    uint32_t myqi = 0;
     if (u.valid) {
         const double2 e = g.epm[u.v];
         const double2 h = g.hsc[u.v];
@@ -522,6 +569,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         mine.sh2 = 2.0 * g.sh[u.v];
         mine.hs = h.x;
         mine.hc = h.y;
+        if (SOFT) myqi = g.idx[u.v];
         if (FP32) {
             const float4 f = g.f32[u.v];
             mine.hep32 = 0.5f * f.x;
@@ -535,7 +583,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
 
     prefetch_windows(A, u, lane, S.wpre);
     uint32_t word = 0;     // next free bitmap word
-    uint32_t found = 0, rechecks = 0, disagree = 0;
+    uint32_t found = 0, rechecks = 0, disagree = 0, lit_und = 0, lit_wrong = 0;
     uint32_t segs = u.segmask;
     for (int seg = 0; segs != 0u; ++seg) {
         const int bit = __builtin_ctz(segs);
@@ -557,6 +605,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
             S.qd[3][rk] = mine.hs;
             S.qd[4][rk] = mine.hc;
             if (FULL) S.qpos[rk] = u.v;
+            if (SOFT) S.qi[rk] = myqi;
             if (FP32) {
                 S.qf[0][rk] = mine.hep32;
                 S.qf[1][rk] = mine.hem32;
@@ -572,7 +621,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         for (uint32_t t0 = 0; t0 < e; t0 += 64u * VT) {
             Cand c[VT];
 #pragma unroll
-            for (int i = 0; i < VT; ++i) load_cand<FP32, WIDE>(g, p[i], c[i]);
+            for (int i = 0; i < VT; ++i) load_cand<FP32, WIDE, SOFT>(g, p[i], c[i]);
             uint32_t pn[VT] = {}, rkn[VT] = {};
             if (t0 + 64u * VT < e) count_positions<VT>(S.flag, S.pb, lane, ne, relu, t0 + 64u * VT, e, bs, be, nj, base, pn, rkn);
 #pragma unroll
@@ -591,8 +640,19 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 }
                 // FP32 filter: test every lane and mask (the loads issue together);
                 // FP64: lanes past the end skip the test (measured faster there)
-                const uint32_t r = FP32 ? (edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) & (act ? 7u : 0u))
-                                        : (act ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
+                uint32_t r;
+                if (SOFT) {
+                    r = 0u;
+                    if (act) {
+                        const double d = q.hs * c[i].hw.y - q.hc * c[i].hw.x;
+                        const double a = q.hep * c[i].ew.y + q.hem * c[i].ew.x;
+                        const double b = (q.sh2 * c[i].sh) * (d * d);
+                        r = soft_test(g, a + b, S.qi[rk[i]], c[i].wi);
+                    }
+                } else {
+                    r = FP32 ? (edge_test<FP32, ABL>(g, q, c[i], p[i], A.exhaustive) & (act ? 31u : 0u))
+                             : (act ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
+                }
                 int flag = (int)(r & 1u);
                 if (FULL) {
                     const uint32_t qp = S.qpos[rk[i]];
@@ -601,6 +661,10 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 if (FP32) {
                     rechecks += (r >> 1) & 1u;
                     disagree += (r >> 2) & 1u;
+                    if (ABL) {
+                        lit_und += (r >> 3) & 1u;
+                        lit_wrong += (r >> 4) & 1u;
+                    }
                 }
                 const uint64_t m = __ballot(flag);
                 found += (uint32_t)__popcll(m);
@@ -621,6 +685,11 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         const uint64_t rc = wave_sum_u64(rechecks), dg = wave_sum_u64(disagree);
         if (lane == 0 && rc) atomicAdd(&A.stats[0], (unsigned long long)rc);
         if (lane == 0 && dg) atomicAdd(&A.stats[1], (unsigned long long)dg);
+        if (ABL) {
+            const uint64_t lu = wave_sum_u64(lit_und), lw = wave_sum_u64(lit_wrong);
+            if (lane == 0 && lu) atomicAdd(&A.stats[2], (unsigned long long)lu);
+            if (lane == 0 && lw) atomicAdd(&A.stats[3], (unsigned long long)lw);
+        }
     }
 }
 

@@ -36,6 +36,7 @@ constexpr int BATCH = 64;        // queries per batch (one wavefront)
 #endif
 constexpr uint32_t UNIT = RHG_UNIT;  // candidates per work unit (upper bound)
 constexpr uint32_t BITMAP_WORDS = UNIT / 64 + 32;  // decision bitmap words per unit
+constexpr int SOFT_LEVELS = 54;  // probability levels 2^-i, i = 0..53, of the general model
 
 enum SrcMode { SRC_SEED = 0, SRC_COORDS = 1, SRC_TABLE = 2 };
 
@@ -76,6 +77,15 @@ struct Geo {
     // points query, in every slab and in both directions, and a pair of two
     // moved points is taken by the one that comes first in sorted order.
     const uint32_t *moved;
+    // General model at temperature T > 0 (Sec. II, Eq. 2), else t2 = 0.  K
+    // and Kw then belong to the enlarged radius Rc beyond which no pair can
+    // be an edge; R stays the model's radius.  t2 = 2T; pseed seeds the
+    // pairs' uniforms; lev[i] (i = 1..53) bounds the cosh distance of a pair
+    // whose uniform is at least 2^-i: at or above lev[i] its probability is
+    // below 2^-i, so it cannot be an edge.
+    double t2;
+    uint64_t pseed;
+    double lev[SOFT_LEVELS];
 };
 
 __device__ __forceinline__ bool bit_of(const uint32_t *bits, uint32_t s) { return (bits[s >> 5] >> (s & 31u)) & 1u; }
@@ -93,6 +103,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+// The uniform deciding pair {lo, hi} of the general model (lo < hi, original
+// indices), as its 53-bit integer k in [1, 2^53] (the uniform is k 2^-53 in
+// (0, 1]): output 2^62 + lo 2^31 + hi of the points' generator, far from the
+// outputs 0 .. 2n - 1 the points take.
+__device__ __forceinline__ uint64_t pair_k(uint64_t seed, uint32_t lo, uint32_t hi) {
+    return (splitmix64(seed, (1ull << 62) + ((uint64_t)lo << 31) + (uint64_t)hi) >> 11) + 1ull;
 }
 
 // Point i of the seeded model (Eq. 1): angle uniform on [0, 2pi), radius by

@@ -41,6 +41,7 @@ struct Ctx {
     hipEvent_t ev[EV_COUNT_] = {};
     void *pinned = nullptr;  // 4 KB host readback area
     int exhaustive = 0;
+    int ablation = 0;  // RHG_OPT_LITERAL_ABLATION
     uint32_t shard_count = 1, shard_index = 0;  // query share of this context (RHG_OPT_SHARD_*)
     uint64_t generation = 0;  // bumped by every count; a plan may emit only while current
 
@@ -66,6 +67,8 @@ struct Request {
     const uint8_t *moved = nullptr;
     const int32_t *old_pairs = nullptr;
     uint64_t m_old = 0;
+    // general model (Sec. II, Eq. 2): temperature, 0 = the threshold model
+    double T = 0.0;
 };
 
 // One planned generation.
@@ -74,11 +77,16 @@ struct Plan {
     int B = 1;
     double p = 0.9;
     double R = 0, K = 0;
+    // general model: T > 0, the pairs' seed, and cosh of the enlarged radius
+    // Rc = R + 74 T that bounds its candidates (K stays cosh R)
+    double T = 0, Kc = 0;
+    uint64_t pseed = 0;
     double c[rhgd::MAX_BANDS + 1] = {};
     bool fp32 = false;
     rhgd::Geo geo;
     rhgk::QueryArgs qa;
     uint64_t n_units = 0, windows = 0, candidates = 0, m = 0, rechecks = 0, disagreements = 0;
+    uint64_t lit_undecided = 0, lit_wrong = 0;  // literal-Eq. 3 ablation counters
     uint64_t generation = 0;
     bool emitted = false;
     double ms[8] = {};
@@ -119,6 +127,10 @@ rhg_status describe(const Request &rq, Plan &pl);
 // Largest disk radius R accepted by every entry point (the FP64 distance test
 // stays finite for all pairs of points up to it).
 constexpr double R_MAX = 354.0;
+// General model: candidates lie within Rc = R + SOFT_CUT * 2T; beyond it
+// y = (x - R) / (2T) > 37, f < e^-37 < 2^-53, and the smallest uniform is
+// 2^-53, so no pair there can be an edge.
+constexpr double SOFT_CUT = 37.0;
 bool radius_in_domain(double R);
 rhg_status request_from_params(const rhg_params *p, Request &rq);
 // Average degree the model approximation gives for (n, alpha, R) (n when alpha <= 1/2).

@@ -226,6 +226,10 @@ extern "C" rhg_status rhg_ctx_set_option(rhg_ctx *ctx, int option, int64_t value
         c->exhaustive = value ? 1 : 0;
         return RHG_OK;
     }
+    if (option == RHG_OPT_LITERAL_ABLATION) {
+        c->ablation = value ? 1 : 0;
+        return RHG_OK;
+    }
     if (option == RHG_OPT_SHARD_COUNT) {
         if (value < 1 || value > 65536) return RHG_EINVAL;
         c->shard_count = (uint32_t)value;
@@ -295,6 +299,10 @@ rhg_status describe(const Request &rq, Plan &pl) {
     if (rq.mode == SRC_SEED && !(rq.alpha > 0.0 && std::isfinite(rq.alpha))) return RHG_EINVAL;
     // the sampler inverts Eq. 1's radius law through sinh(alpha R / 2)
     if (rq.mode == SRC_SEED && !std::isfinite(std::sinh(rq.alpha * rq.R / 2.0))) return RHG_EINVAL;
+    // the general model: 0 < T < 1, FP64, the enlarged radius in the domain
+    if (std::isnan(rq.T) || rq.T < 0.0 || rq.T >= 1.0) return RHG_EINVAL;
+    if (rq.T > 0.0 && (rq.precision != RHG_FP64 || rq.moved || !radius_in_domain(rq.R + 2.0 * SOFT_CUT * rq.T)))
+        return RHG_EINVAL;
     int B = rq.num_bands ? (int)rq.num_bands : default_bands(rq.n);
     double p = rq.band_ratio > 0.0 ? rq.band_ratio : 0.9;
     if (B < 1 || B > MAX_BANDS) return RHG_EINVAL;
@@ -305,6 +313,9 @@ rhg_status describe(const Request &rq, Plan &pl) {
     pl.R = rq.R;
     pl.K = std::cosh(rq.R);
     pl.fp32 = rq.precision == RHG_FP32_RECHECK;
+    pl.T = rq.T;
+    pl.pseed = rq.seed;
+    pl.Kc = rq.T > 0.0 ? std::cosh(rq.R + 2.0 * SOFT_CUT * rq.T) : 0.0;
     return RHG_OK;
 }
 
@@ -331,6 +342,19 @@ void geo_static(const Plan &pl, Geo &g) {
     g.Kw = pl.K * (1.0 + 0x1p-30);
     g.klo32 = round_down_f32(pl.K * (1.0 - 0x1p-20));
     g.khi32 = round_up_f32(pl.K * (1.0 + 0x1p-20));
+    if (pl.T > 0.0) {
+        // general model: windows and the first test for the enlarged radius;
+        // lev[i] = cosh(R + 2T ln(2^i - 1)) raised by 2^-30, where f = 2^-i:
+        // a pair at or beyond it has f < 2^-i (the margin moves f by a
+        // relative 2^-31 / T at least, far above the rounding of f)
+        g.K = pl.Kc;
+        g.Kw = pl.Kc * (1.0 + 0x1p-30);
+        g.t2 = 2.0 * pl.T;
+        g.pseed = pl.pseed;
+        g.lev[0] = INFINITY;
+        for (int i = 1; i < SOFT_LEVELS; ++i)
+            g.lev[i] = std::cosh(pl.R + 2.0 * pl.T * std::log(std::ldexp(1.0, i) - 1.0)) * (1.0 + 0x1p-30);
+    }
     for (int j = 0; j <= pl.B; ++j) {
         g.c[j] = pl.c[j];
         g.shc[j] = std::sinh(pl.c[j]);
@@ -517,7 +541,7 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     qa.bits = bits;
     qa.unit_edge_off = ueoff;
     qa.stats = stats;
-    qa.exhaustive = c->exhaustive;
+    qa.exhaustive = (c->ablation && pl.fp32 && !update) ? 2 : c->exhaustive;
     RHG_BUF(ukey, uint32_t, S_UKEY, std::max<uint64_t>(U, 1));
     RHG_BUF(uorder, uint32_t, S_UORDER, std::max<uint64_t>(U, 1));
     RHG_BUF(ukey2, uint32_t, S_UKEY2, std::max<uint64_t>(U, 1));
@@ -567,7 +591,8 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     }
     RHG_HIP(hipEventRecord(c->ev[EV_SCAN1], st));
     RHG_HIP(hipMemcpyAsync(pin + 2, ueoff + U, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    RHG_HIP(hipMemcpyAsync(pin + 3, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    // (pinned words: 0-2 totals, 6 kept pairs, 16-21 the share's cut, 24-27 the counters)
+    RHG_HIP(hipMemcpyAsync(pin + 24, stats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     uint32_t *usort_err = (uint32_t *)((char *)c->pinned + 1028);
     *usort_err = 0;
     if (qa.unit_order)
@@ -578,8 +603,10 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     if (*keep_err_host != 0) return RHG_EINVAL;  // an old pair names a point outside 0..n-1
     pl.m_keep = pin[6];
     pl.m = pin[2] + pl.m_keep;
-    pl.rechecks = pin[3];
-    pl.disagreements = pin[4];
+    pl.rechecks = pin[24];
+    pl.disagreements = pin[25];
+    pl.lit_undecided = qa.exhaustive == 2 ? pin[26] : 0;
+    pl.lit_wrong = qa.exhaustive == 2 ? pin[27] : 0;
     return RHG_OK;
 }
 
@@ -865,6 +892,63 @@ extern "C" rhg_status rhg_count(rhg_ctx *ctx, const rhg_params *params, rhg_grap
     return s;
 }
 
+// General model (Sec. II, Eq. 2) from rhg_params: a kbar request takes R
+// from getTargetRadius at kbar sin(pi T) / (pi T): at temperature T the
+// expected degree of a disk of radius R grows by pi T / sin(pi T) to leading
+// order (the integral of e^{x/2} against Eq. 2's probability over the
+// distance, against the step of T = 0).
+static rhg_status soft_request(const rhg_params *p, double T, Request &rq) {
+    if (!p || !(T > 0.0 && T < 1.0)) return RHG_EINVAL;
+    rhg_params q = *p;
+    if (!(q.R > 0.0)) {
+        if (std::isnan(q.kbar)) return RHG_EINVAL;
+        const double pi = 3.14159265358979323846;
+        q.kbar = p->kbar * std::sin(pi * T) / (pi * T);
+    }
+    rhg_status s = request_from_params(&q, rq);
+    if (s != RHG_OK) return s;
+    rq.T = T;
+    return RHG_OK;
+}
+
+extern "C" rhg_status rhg_generate_soft(rhg_ctx *ctx, const rhg_params *params, double T, rhg_graph **out) {
+    if (!out) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = soft_request(params, T, rq);
+    if (s != RHG_OK) return s;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_count_soft(rhg_ctx *ctx, const rhg_params *params, double T, rhg_graph **plan,
+                                     uint64_t *m) {
+    if (!plan || !m) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = soft_request(params, T, rq);
+    if (s != RHG_OK) return s;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, false, &g, m);
+    if (s == RHG_OK) *plan = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
+extern "C" rhg_status rhg_generate_soft_from_table(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
+                                                   const double *table5xn, double R, double T, uint64_t seed,
+                                                   int on_device, rhg_graph **out) {
+    if (!table5xn || !out || !(T > 0.0 && T < 1.0)) return RHG_EINVAL;
+    Request rq;
+    rhg_status s = coords_request(n, theta, r, table5xn, R, RHG_FP64, on_device, rq);
+    if (s != RHG_OK) return s;
+    rq.T = T;
+    rq.seed = seed;
+    Graph *g = nullptr;
+    s = generate(reinterpret_cast<Ctx *>(ctx), rq, true, &g, nullptr);
+    if (s == RHG_OK) *out = reinterpret_cast<rhg_graph *>(g);
+    return s;
+}
+
 extern "C" rhg_status rhg_emit(rhg_ctx *ctx, rhg_graph *plan, int32_t *dev_pairs, uint64_t capacity_pairs) {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     Graph *g = reinterpret_cast<Graph *>(plan);
@@ -954,6 +1038,8 @@ extern "C" rhg_status rhg_graph_stats(const rhg_graph *gr, rhg_stats *st) {
     st->rechecks = g->pl.rechecks;
     st->windows = g->pl.windows;
     st->disagreements = g->pl.disagreements;
+    st->literal_undecided = g->pl.lit_undecided;
+    st->literal_wrong = g->pl.lit_wrong;
     for (int k = 0; k < 8; ++k) st->ms[k] = g->pl.ms[k];
     st->bytes_moved = algorithmic_bytes(g->pl);
     st->count_kernel_ms = g->pl.count_kernel_ms;

@@ -23,6 +23,7 @@ RHG_FP64, RHG_FP32_RECHECK = 0, 1
 RHG_OPT_FP32_EXHAUSTIVE = 1
 RHG_OPT_SHARD_COUNT = 2
 RHG_OPT_SHARD_INDEX = 3
+RHG_OPT_LITERAL_ABLATION = 4
 
 
 class RhgError(RuntimeError):
@@ -41,7 +42,8 @@ class rhg_stats(ctypes.Structure):
     _fields_ = [("edges", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
                 ("windows", ctypes.c_uint64), ("disagreements", ctypes.c_uint64),
                 ("ms", ctypes.c_double * 8), ("bytes_moved", ctypes.c_uint64),
-                ("count_kernel_ms", ctypes.c_double)]
+                ("count_kernel_ms", ctypes.c_double), ("literal_undecided", ctypes.c_uint64),
+                ("literal_wrong", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms"}
@@ -102,6 +104,9 @@ def load(path: Optional[str] = None):
         "rhg_count": (i32, [vp, P(rhg_params), P(vp), P(u64)]),
         "rhg_emit": (i32, [vp, vp, vp, u64]),
         "rhg_generate_noalloc": (i32, [vp, P(rhg_params), vp, u64, P(u64)]),
+        "rhg_generate_soft": (i32, [vp, P(rhg_params), d, P(vp)]),
+        "rhg_count_soft": (i32, [vp, P(rhg_params), d, P(vp), P(u64)]),
+        "rhg_generate_soft_from_table": (i32, [vp, u64, vp, vp, vp, d, d, u64, i32, P(vp)]),
         "rhg_graph_num_edges": (i32, [vp, P(u64)]),
         "rhg_graph_num_points": (i32, [vp, P(u64)]),
         "rhg_graph_radius": (i32, [vp, P(d)]),
@@ -282,6 +287,35 @@ def rhg_count(ctx, p: rhg_params) -> Tuple[ctypes.c_void_p, int]:
 def rhg_emit(ctx, plan, dev_pairs, capacity_pairs: int):
     """dev_pairs: a torch int32 tensor on the GPU (>= 2*m elements) or a device address."""
     _check(load().rhg_emit(ctx, plan, _ptr(dev_pairs), int(capacity_pairs)), "rhg_emit")
+
+
+def rhg_generate_soft(ctx, p: rhg_params, T: float) -> ctypes.c_void_p:
+    """General model at temperature T (Sec. II, Eq. 2); p.seed also seeds the pairs' uniforms."""
+    g = ctypes.c_void_p()
+    _check(load().rhg_generate_soft(ctx, ctypes.byref(p), float(T), ctypes.byref(g)), "rhg_generate_soft")
+    return g
+
+
+def rhg_count_soft(ctx, p: rhg_params, T: float) -> Tuple[ctypes.c_void_p, int]:
+    g = ctypes.c_void_p()
+    m = ctypes.c_uint64()
+    _check(load().rhg_count_soft(ctx, ctypes.byref(p), float(T), ctypes.byref(g), ctypes.byref(m)),
+           "rhg_count_soft")
+    return g, m.value
+
+
+def rhg_generate_soft_from_table(ctx, theta, r, table5xn, R: float, T: float, seed: int) -> ctypes.c_void_p:
+    on_dev = int(not isinstance(theta, np.ndarray))
+    if isinstance(theta, np.ndarray):
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        table5xn = np.ascontiguousarray(table5xn, dtype=np.float64)
+    n = len(theta)
+    g = ctypes.c_void_p()
+    _check(load().rhg_generate_soft_from_table(ctx, n, _ptr(theta), _ptr(r), _ptr(table5xn), float(R), float(T),
+                                               int(seed) & (2**64 - 1), on_dev, ctypes.byref(g)),
+           "rhg_generate_soft_from_table")
+    return g
 
 
 def rhg_generate_noalloc(ctx, p: rhg_params, dev_pairs, capacity_pairs: int) -> int:
