@@ -10,13 +10,18 @@ preallocated device buffer (rhg_count + rhg_emit).  The FP64 form gives
 reported beside it (its edge list is checked byte-identical).
 
 Also reported: per-phase device times (HIP events on the library stream),
-the roofline of the dominant kernel, the CPU oracle on a bounded sample of
-the same workload (cpu_baseline), the request server on a stream of
-2000 mixed requests (serving): closed-loop saturation throughput X, then
-Poisson arrivals at 0.7 X with p50/p99 latency and aggregate edges/s; one
-GPU's share of an 8-GPU run (share: whole table, 1/8 of the queries); and
-the dynamic model's movement step with the regeneration of the moved graph
-(dynamic).
+the roofline of the dominant kernel (and the other query kernel, and the
+whole step), the CPU oracle on the same workload (cpu_baseline: the whole
+generation on the host cores, median of 3), the other fixed workloads
+(configs: n = 10^6 and the exponent sweep at n = 4 10^6, both precision
+forms, recheck fractions, HBM fractions), the FP32 ablation (fp32_ablation:
+the filter used against Eq. 3 as printed in FP32), the general model at
+T > 0 (soft), the request server on a stream of 2000 mixed requests
+(serving): closed-loop saturation throughput X, then Poisson arrivals at
+0.7 X and at fixed rates with p50/p99 latency and aggregate edges/s; one
+GPU's share of an 8-GPU run (share: whole table, 1/8 of the queries); the
+dynamic model's movement step with the update and the regeneration of the
+moved graph (dynamic); and the CSR adjacency (csr).
 """
 from __future__ import annotations
 
@@ -34,20 +39,37 @@ METRIC = "edges/s at n=1e7, kbar=100 (FP64 vs FP32+recheck); p50/p99 request lat
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(n, windows, units, m):
-    """Algorithmic HBM bytes per launch of the two query kernels:
-    count reads the 5 FP64 table columns once per point (40 B), each window
-    record (8 B) and writes one count per unit (4 B); emit reads the same plus
-    the original index (4 B per point) and writes one int32 pair per edge (8 B)."""
-    count = 40 * n + 8 * windows + 4 * units
-    emit = 44 * n + 8 * windows + 8 * m
+def kernel_bytes(n, m):
+    """Algorithmic HBM bytes per launch of the two query kernels, as the
+    method needs them (per point and per edge, independent of the plan):
+    count reads the sorted FP64 table once (6 x 8 B per point: angle, exp(r),
+    exp(-r), sinh r, sin and cos of the half angle) and writes a count per
+    point (4 B); emit reads the table once more, the offsets (8 B per point)
+    and writes one int32 pair per edge (8 B)."""
+    count = 52 * n
+    emit = 56 * n + 8 * m
     return count, emit
 
 
-def run_gpu(args):
+def step_bytes(n, m):
+    """Algorithmic HBM bytes of one whole generation: read the coordinates
+    (16 B per point), write the sorted table (48 B) and read it in count and
+    emit (2 x 48 B), counts and offsets (12 B), and the edges (8 B each):
+    172 B per point + 8 B per edge."""
+    return 172 * n + 8 * m
+
+
+def run_gpu(args, n=None, alpha=None, kbar=None, steps=None, warmup=None, tag=""):
+    """Times `steps` whole generations (after `warmup`) in each precision form
+    through rhg_count + rhg_emit into one preallocated device buffer."""
     import torch
     from paper_1606_09481_amd import rhg
 
+    n = args.n if n is None else n
+    alpha = args.alpha if alpha is None else alpha
+    kbar = args.kbar if kbar is None else kbar
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     rhg.load()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -56,9 +78,9 @@ def run_gpu(args):
     out = None
     ref_edges = None
     for prec, name in ((rhg.RHG_FP64, "fp64"), (rhg.RHG_FP32_RECHECK, "fp32_recheck")):
-        p = rhg.params(args.n, args.alpha, kbar=args.kbar, seed=args.seed, precision=prec)
+        p = rhg.params(n, alpha, kbar=kbar, seed=args.seed, precision=prec)
         times, stats = [], []
-        for it in range(args.warmup + args.steps):
+        for it in range(warmup + steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             plan, m = rhg.rhg_count(ctx, p)
@@ -77,10 +99,11 @@ def run_gpu(args):
             st = rhg.rhg_graph_stats(plan)
             R = rhg.rhg_graph_radius(plan)
             rhg.rhg_graph_free(plan)
-            if it >= args.warmup:
+            if it >= warmup:
                 times.append(t1 - t0)
                 stats.append(st)
-            print("[bench] %s step %d: %.3f ms, m=%d" % (name, it, 1e3 * (t1 - t0), m), file=sys.stderr, flush=True)
+            print("[bench] %s%s step %d: %.3f ms, m=%d" % (tag, name, it, 1e3 * (t1 - t0), m), file=sys.stderr,
+                  flush=True)
         if name == "fp64":
             ref_edges = out[: 2 * m].clone()
         else:
@@ -274,6 +297,127 @@ def run_dynamic(args):
     return res
 
 
+def summarize(res, n):
+    """Edges/s of both precision forms, the recheck fraction and the HBM
+    fractions (algorithmic bytes over time) of one timed configuration."""
+    f64, f32 = res["fp64"], res["fp32_recheck"]
+    m = f64["m"]
+    cb, eb = kernel_bytes(n, m)
+    sb = step_bytes(n, m)
+    frac = lambda b, ms: b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    return {
+        "edges": m, "R": f64["R"], "candidates": f64["candidates"], "windows": f64["windows"],
+        "fp64": {"edges_per_s": f64["edges_per_s"], "ms_per_step": 1e3 * f64["s_per_step"],
+                 "count_kernel_ms": f64["count_kernel_ms"], "emit_ms": f64["phases_ms"]["emit"],
+                 "device_ms": f64["phases_ms"]["device_total"]},
+        "fp32_recheck": {"edges_per_s": f32["edges_per_s"], "ms_per_step": 1e3 * f32["s_per_step"],
+                         "count_kernel_ms": f32["count_kernel_ms"], "rechecks": f32["rechecks"],
+                         "recheck_fraction": f32["rechecks"] / max(1, f32["candidates"]),
+                         "identical_to_fp64": res.get("fp32_identical_to_fp64")},
+        "hbm_frac": {"step": frac(sb, 1e3 * f64["s_per_step"]), "count": frac(cb, f64["count_kernel_ms"]),
+                     "emit": frac(eb, f64["phases_ms"]["emit"]), "step_bytes": sb,
+                     "what": "algorithmic bytes (172 B/point + 8 B/edge per step; count 52 B/point; emit "
+                             "56 B/point + 8 B/edge) over the FP64 host step time and the kernels' HIP-event "
+                             "times, against 8 TB/s"},
+    }
+
+
+CONFIGS = [(1_000_000, 1.0, 20.0), (4_000_000, 0.55, 64.0), (4_000_000, 1.0, 64.0), (4_000_000, 1.5, 64.0)]
+
+
+def run_configs(args):
+    """The other fixed workloads: n = 10^6, alpha = 1, kbar = 20 and the
+    exponent sweep n = 4 10^6, kbar = 64, alpha in {0.55, 1, 1.5}, both
+    precision forms (2 warm-up + 5 timed steps each)."""
+    out = {}
+    for (n, alpha, kbar) in CONFIGS:
+        res = run_gpu(args, n=n, alpha=alpha, kbar=kbar, steps=5, warmup=2, tag="n=%d a=%g " % (n, alpha))
+        out["n=%d alpha=%g kbar=%g" % (n, alpha, kbar)] = summarize(res, n)
+    return out
+
+
+def run_ablation(args):
+    """The FP32 forms side by side on every candidate of one generation:
+    the cancellation-free filter actually used (its margin mu = 2^-20 leaves
+    `recheck_fraction` undecided) against Eq. 3 as printed in FP32
+    (undecided under its sound margin 8 u32 (A + S), and the error rate of
+    its plain FP32 decision against the FP64 test)."""
+    from paper_1606_09481_amd import rhg
+    import torch
+    rhg.load()
+    ctx = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    rhg.rhg_ctx_set_option(ctx, rhg.RHG_OPT_LITERAL_ABLATION, 1)
+    out = {}
+    try:
+        for (n, alpha, kbar) in [(args.n, args.alpha, args.kbar)] + CONFIGS:
+            plan, m = rhg.rhg_count(ctx, rhg.params(n, alpha, kbar=kbar, seed=args.seed,
+                                                    precision=rhg.RHG_FP32_RECHECK))
+            st = rhg.rhg_graph_stats(plan)
+            rhg.rhg_graph_free(plan)
+            c = max(1, st["candidates"])
+            out["n=%d alpha=%g kbar=%g" % (n, alpha, kbar)] = {
+                "candidates": st["candidates"], "edges": m,
+                "filter_recheck_fraction": st["rechecks"] / c, "filter_disagreements": st["disagreements"],
+                "literal_undecided_fraction": st["literal_undecided"] / c,
+                "literal_raw_error_rate": st["literal_wrong"] / c}
+            print("[bench] ablation n=%d alpha=%g: filter rechecks %.2e, literal undecided %.3f, literal wrong %.2e"
+                  % (n, alpha, st["rechecks"] / c, st["literal_undecided"] / c, st["literal_wrong"] / c),
+                  file=sys.stderr, flush=True)
+    finally:
+        rhg.rhg_ctx_destroy(ctx)
+    return out
+
+
+SOFT_CONFIGS = [(1_000_000, 1.0, 20.0, 0.1), (10_000_000, 0.75, 100.0, 0.05)]
+
+
+def run_soft(args):
+    """The general model at temperature T > 0 (Eq. 2): rhg_count_soft +
+    rhg_emit into a preallocated buffer, 1 warm-up + 3 timed steps."""
+    import torch
+    from paper_1606_09481_amd import rhg
+    rhg.load()
+    ctx = rhg.rhg_ctx_create(0, torch.cuda.current_stream())
+    res = {}
+    out = None
+    try:
+        for (n, alpha, kbar, T) in SOFT_CONFIGS:
+            p = rhg.params(n, alpha, kbar=kbar, seed=args.seed)
+            ts = []
+            for it in range(1 + 3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan, m = rhg.rhg_count_soft(ctx, p, T)
+                if out is None or out.numel() < 2 * m:
+                    rhg.rhg_graph_free(plan)
+                    out = None
+                    torch.cuda.synchronize()
+                    out = torch.empty(2 * m + 1024, dtype=torch.int32, device="cuda")
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    plan, m = rhg.rhg_count_soft(ctx, p, T)
+                rhg.rhg_emit(ctx, plan, out, out.numel() // 2)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = rhg.rhg_graph_stats(plan)
+                R = rhg.rhg_graph_radius(plan)
+                rhg.rhg_graph_free(plan)
+                if it >= 1:
+                    ts.append(t1 - t0)
+            t = sum(ts) / len(ts)
+            res["n=%d alpha=%g kbar=%g T=%g" % (n, alpha, kbar, T)] = {
+                "edges_per_s": m / t, "ms_per_step": 1e3 * t, "edges": m, "avg_degree": 2.0 * m / n, "R": R,
+                "candidates": st["candidates"], "candidates_per_edge": st["candidates"] / max(1, m),
+                "count_kernel_ms": st["count_kernel_ms"], "emit_ms": st["ms"][6]}
+            print("[bench] soft n=%d T=%g: %.3f ms, m=%d, %.1f candidates/edge" % (
+                n, T, 1e3 * t, m, st["candidates"] / max(1, m)), file=sys.stderr, flush=True)
+    finally:
+        rhg.rhg_ctx_destroy(ctx)
+        del out
+        torch.cuda.empty_cache()
+    return res
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_traffic_n1e7_a075_k100.md")
 KERNEL_SOURCES = ["query_dev.h", "query.hip", "rhg_device.h", "rhg_kernels.h"]
 
@@ -316,7 +460,8 @@ def copy_calibration(mib):
 def serving_requests(rhg, count, seed):
     """The serving mix: n log-uniform in [1e3, 2e6], alpha uniform in
     [0.55, 1.5], kbar uniform integer in 6..64 (combinations whose average
-    degree the model cannot reach are drawn again), request i seeded base+i."""
+    degree the model cannot reach are drawn again), request i seeded base+i;
+    every third request in the FP32-filter form, the others FP64."""
     import numpy as np
     rng = np.random.default_rng(seed)
     out = []
@@ -328,7 +473,8 @@ def serving_requests(rhg, count, seed):
             rhg.rhg_target_radius(n, alpha, kbar)
         except rhg.RhgError:
             continue
-        out.append(rhg.params(n, alpha, kbar=kbar, seed=1000 + len(out)))
+        prec = rhg.RHG_FP32_RECHECK if len(out) % 3 == 2 else rhg.RHG_FP64
+        out.append(rhg.params(n, alpha, kbar=kbar, seed=1000 + len(out), precision=prec))
     return out
 
 
@@ -381,6 +527,16 @@ def run_serving(args):
         lam = 0.7 * X
         arrivals = poisson_arrivals(len(reqs), lam, args.seed + 7)
         T, lat, edges2 = _serve(rhg, srv, reqs, arrivals)
+        # the same stream at a fixed arrival rate, comparable across runs
+        fixed = {}
+        for rate in args.serve_rates:
+            Tf, latf, edgesf = _serve(rhg, srv, reqs, poisson_arrivals(len(reqs), rate, args.seed + 7))
+            latf = np.array(latf)
+            fixed["%g" % rate] = {"p50": float(np.percentile(latf, 50)), "p99": float(np.percentile(latf, 99)),
+                                  "mean": float(latf.mean()), "edges_per_s": edgesf / Tf,
+                                  "achieved_req_per_s": len(reqs) / Tf}
+            print("[bench] serving at %.0f req/s: p50 %.3f ms p99 %.3f ms" % (rate, fixed["%g" % rate]["p50"],
+                  fixed["%g" % rate]["p99"]), file=sys.stderr, flush=True)
         cnt = rhg.rhg_server_counters(srv)
     finally:
         rhg.rhg_server_destroy(srv)
@@ -390,7 +546,8 @@ def run_serving(args):
           % (X, edges / T_sat, lam, pct(lat, 50), pct(lat, 99)), file=sys.stderr, flush=True)
     return {
         "requests": len(reqs), "edges": int(edges), "budget_bytes": args.serve_budget_gb << 30,
-        "mix": "n log-uniform [1e3, 2e6], alpha U[0.55, 1.5], kbar U{6..64}, request i seed 1000+i, FP64",
+        "mix": "n log-uniform [1e3, 2e6], alpha U[0.55, 1.5], kbar U{6..64}, request i seed 1000+i, "
+               "every third request FP32 filter + FP64 recheck, the others FP64",
         "saturation_req_per_s": X, "saturation_edges_per_s": edges / T_sat,
         "arrival_rate_req_per_s": lam, "arrivals": "Poisson, seed %d" % (args.seed + 7),
         "edges_per_s": edges2 / T, "wall_s": T,
@@ -398,36 +555,47 @@ def run_serving(args):
                        "small_p50": pct(lat[small], 50), "small_p99": pct(lat[small], 99),
                        "large_p50": pct(lat[~small], 50), "large_p99": pct(lat[~small], 99)},
         "latency_definition": "submit (at arrival) to results host-visible after the device finished",
+        "fixed_rate": fixed, "fixed_rate_arrivals": "Poisson at the stated rate (req/s), seed %d" % (args.seed + 7),
         "small_fraction": float(small.mean()), "counters": cnt,
     }
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(args, m_full):
-    """The oracle as it stands on the host cores: sample + table + slab sort of
-    all n points timed in full; the band sweep on the first `frac` of the
-    queries (i.i.d. points: a uniform sample), scaled by 1/frac."""
+    """The oracle as it stands on the host cores: sampling, table, slab sort
+    and the band sweep over every query of the benchmark workload, timed in
+    full `cpu_runs` times on all the cores the job may use (median); and on
+    one thread, the same phases with the sweep over 1% of the queries (i.i.d.
+    points: a uniform sample), scaled by 100 (a labelled projection)."""
     import oracle
-    frac = args.cpu_frac
     threads = oracle.default_threads()
-    t0 = time.perf_counter()
     R = oracle.target_radius(args.n, args.alpha, args.kbar)
-    th, r = oracle.sample(args.n, args.alpha, R, args.seed)
-    tab = oracle.table(th, r)
-    t1 = time.perf_counter()
-    oracle.band_sweep(th, r, tab, R, math.cosh(R), threads=threads, q0=0, q1=0)   # slab sort alone
-    t2 = time.perf_counter()
-    q1 = int(args.n * frac)
-    e = oracle.band_sweep(th, r, tab, R, math.cosh(R), threads=threads, q0=0, q1=q1)
-    t3 = time.perf_counter()
-    setup = (t1 - t0) + (t2 - t1)
-    sweep = max((t3 - t2) - (t2 - t1), 1e-9)
-    T_full = setup + sweep / frac
-    m_est = len(e) / frac
-    # the same on one thread: sampling, table and slab sort of all points,
-    # band sweep over a tenth of the sample
-    f1 = frac / 10
+    runs = []
+    m = None
+    for k in range(max(1, args.cpu_runs)):
+        t0 = time.perf_counter()
+        th, r = oracle.sample(args.n, args.alpha, R, args.seed, threads=threads)
+        tab = oracle.table(th, r, threads=threads)
+        e = oracle.band_sweep(th, r, tab, R, math.cosh(R), threads=threads)
+        t1 = time.perf_counter()
+        m = len(e)
+        runs.append(t1 - t0)
+        del th, r, tab, e
+        print("[bench] cpu oracle run %d: %.2f s, m=%d" % (k, t1 - t0, m), file=sys.stderr, flush=True)
+    T_med = sorted(runs)[len(runs) // 2]
+    # one thread: whole setup, sweep over 1% of the queries
+    f1 = 0.01
     q1s = int(args.n * f1)
-    t3b = time.perf_counter()
+    t3 = time.perf_counter()
     th1, r1 = oracle.sample(args.n, args.alpha, R, args.seed, threads=1)
     tab1 = oracle.table(th1, r1, threads=1)
     t4 = time.perf_counter()
@@ -436,18 +604,19 @@ def cpu_baseline(args, m_full):
     e1 = oracle.band_sweep(th1, r1, tab1, R, math.cosh(R), threads=1, q0=0, q1=q1s)
     t6 = time.perf_counter()
     sweep1 = max((t6 - t5) - (t5 - t4), 1e-9)
-    T1 = (t4 - t3b) + (t5 - t4) + sweep1 / f1
+    T1 = (t4 - t3) + (t5 - t4) + sweep1 / f1
     m1 = len(e1) / f1
-    return {"value": m_est / T_full, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": "n=%d alpha=%g kbar=%g seed=%d: sampling, table and slab sort of all points timed in full "
-                      "(%.1f s); band sweep over queries [0, %d) (%.0f%%, %d edges, %.1f s) scaled by 1/%.2f; "
-                      "projected %.1f s for ~%.3g edges" % (args.n, args.alpha, args.kbar, args.seed, setup, q1,
-                                                            100 * frac, len(e), t3 - t2, frac, T_full, m_est),
-            "single_thread": {"value": m1 / T1, "unit": "edges/s", "cores": 1,
+    return {"value": m / T_med, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "sample": "n=%d alpha=%g kbar=%g seed=%d, the whole generation: sampling, table, slab sort and the "
+                      "band sweep over every query (%d edges; the GPU's m = %d), median of %d runs on %d threads "
+                      "(%s s)" % (args.n, args.alpha, args.kbar, args.seed, m, m_full, len(runs), threads,
+                                  ", ".join("%.2f" % x for x in runs)),
+            "single_thread": {"value": m1 / T1, "unit": "edges/s", "cores": 1, "kind": "oracle, projected",
                               "sample": "sampling, table and slab sort of all points on one thread (%.1f s); "
-                                        "band sweep over queries [0, %d) (%.1f%%, %d edges, %.1f s) scaled by "
-                                        "1/%.3f; projected %.1f s" % (t5 - t3b, q1s, 100 * f1, len(e1), t6 - t5,
-                                                                      f1, T1)}}
+                                        "band sweep over queries [0, %d) (1%%, %d edges, %.1f s) scaled by 100; "
+                                        "projected %.1f s for the whole generation" % (t5 - t3, q1s, len(e1),
+                                                                                      t6 - t5, T1)}}
 
 
 def main():
@@ -468,6 +637,12 @@ def main():
                          "scales HBM byte counters under rocprofv3 --pmc)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[8000.0],
+                    help="fixed Poisson arrival rates (req/s) at which to also report latency")
+    ap.add_argument("--no-configs", action="store_true", help="skip the n = 1e6 and n = 4e6 workloads")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the literal-Eq. 3 FP32 ablation")
+    ap.add_argument("--no-soft", action="store_true", help="skip the T > 0 workloads")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="full oracle runs for cpu_baseline (median)")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-model timing")
     ap.add_argument("--no-csr", action="store_true", help="skip the CSR adjacency timing")
     ap.add_argument("--shares", type=int, default=8,
@@ -489,7 +664,7 @@ def main():
         copy_calibration(args.copy_calibration)
     f64, f32 = res["fp64"], res["fp32_recheck"]
     n = args.n
-    cnt_b, emit_b = kernel_bytes(n, f64["windows"], 0, f64["m"])
+    cnt_b, emit_b = kernel_bytes(n, f64["m"])
     ph = f64["phases_ms"]
     bench_cfg = (n, args.alpha, args.kbar, args.seed) == (10_000_000, 0.75, 100.0, 1)
 
@@ -524,9 +699,20 @@ def main():
                          "rechecks": f32["rechecks"], "recheck_fraction": f32["rechecks"] / max(1, f32["candidates"]),
                          "identical_to_fp64": res.get("fp32_identical_to_fp64"), "phases_ms": f32["phases_ms"]},
         "roofline": roof,
+        # the whole step against the HBM roofline: 172 B per point + 8 B per edge of algorithmic bytes
+        "step_roofline": {"bound": "hbm", "algorithmic_bytes": step_bytes(n, f64["m"]),
+                          "ms_per_step": 1e3 * f64["s_per_step"], "device_ms": ph["device_total"],
+                          "frac": step_bytes(n, f64["m"]) / f64["s_per_step"] / 1e9 / HBM_PEAK_GBS,
+                          "roofline_ms": step_bytes(n, f64["m"]) / (HBM_PEAK_GBS * 1e9) * 1e3},
     }
     if serving is not None:
         line["serving"] = serving
+    if not args.no_configs:
+        line["configs"] = run_configs(args)
+    if not args.no_ablation:
+        line["fp32_ablation"] = run_ablation(args)
+    if not args.no_soft:
+        line["soft"] = run_soft(args)
     if args.shares > 1:
         line["share"] = run_shares(args)
     if not args.no_dynamic:
