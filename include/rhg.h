@@ -27,7 +27,8 @@
  *     build but otherwise unspecified: compare edge lists as sets.
  *   - The distance test is evaluated in IEEE binary64 in a fixed order
  *     (cosh(r_u - r_v) + 2 sinh r_u sinh r_v sin^2(dtheta/2), from per-point
- *     exp(r), exp(-r), sinh r, sin(theta/2), cos(theta/2)), strict "< cosh R".
+ *     exp(r), exp(-r), sin(theta/2), cos(theta/2), with sinh r taken as
+ *     (exp(r) - exp(-r)) / 2 of the first two), strict "< cosh R".
  *     RHG_FP32_RECHECK decides the same predicate with an FP32 filter and a
  *     proven margin and re-decides the undecided pairs in FP64: its edge set
  *     is identical to RHG_FP64's.
@@ -195,9 +196,11 @@ rhg_status rhg_generate_from_coords(rhg_ctx *ctx, uint64_t n, const double *thet
 /* Same, with the per-point table supplied instead of computed on the device:
  * table5xn = [exp(r) | exp(-r) | sinh r | sin(theta/2) | cos(theta/2)], each
  * n doubles, row-major (5 x n), same memory kind as theta/r.  The distance
- * test reads exactly these bits, so any caller-side evaluation of the same
- * table gives a bit-identical edge set.  theta and r still place points in
- * slabs and windows. */
+ * test reads exactly the bits of columns 0, 1, 3 and 4, so any caller-side
+ * evaluation of the same table gives a bit-identical edge set; it takes
+ * sinh r as (exp(r) - exp(-r)) / 2 of columns 0 and 1 (column 2 is not read;
+ * rhg_graph_copy_points fills it with that value).  theta and r still place
+ * points in slabs and windows. */
 rhg_status rhg_generate_from_table(rhg_ctx *ctx, uint64_t n, const double *theta, const double *r,
                                    const double *table5xn, double R, rhg_precision precision, int on_device,
                                    rhg_graph **out);

@@ -26,7 +26,8 @@
  *        definition.
  *   orc_table                            -- per-point FP64 values the
  *        distance test reads (exp(r), exp(-r), sinh r, sin(theta/2),
- *        cos(theta/2)).
+ *        cos(theta/2)), sinh r taken as (exp(r) - exp(-r)) / 2 of the first
+ *        two.
  *   orc_coshdist / orc_is_edge           -- hyperbolic law of cosines (Sec. II,
  *        Eq. 3) against cosh R, evaluated in the cancellation-free form
  *        cosh(r_u - r_v) + 2 sinh r_u sinh r_v sin^2(dtheta/2).
@@ -188,14 +189,19 @@ int orc_sample(uint64_t n, double alpha, double R, uint64_t seed, double *theta,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Per-point table for the distance test.                                     */
+/* Per-point table for the distance test.  sinh r is taken as                 */
+/* (e^r - e^-r) / 2 from the two exponentials of the table (one rounded       */
+/* subtraction, an exact halving), so that the distance test needs only four  */
+/* independent values per point.  For small r the subtraction cancels: the    */
+/* error is then absolute, at most about 3 u cosh r, and the term it feeds,   */
+/* 2 sinh r_u sinh r_v sin^2(dtheta/2), stays within a few u of cosh dist.    */
 /* ------------------------------------------------------------------------- */
 void orc_table(uint64_t n, const double *theta, const double *r,
                double *ep, double *em, double *sh, double *hs, double *hc) {
     for (uint64_t i = 0; i < n; ++i) {
         ep[i] = exp(r[i]);
         em[i] = exp(-r[i]);
-        sh[i] = sinh(r[i]);
+        sh[i] = 0.5 * (ep[i] - em[i]);
         hs[i] = sin(theta[i] / 2.0);
         hc[i] = cos(theta[i] / 2.0);
     }

@@ -138,7 +138,7 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
         qv = key & QMASK;
         thv = g.th[s];
         const double2 e = g.epm[s];
-        const double shv = g.sh[s];
+        const double shv = 0.5 * (e.x - e.y);  // sinh r as the distance test takes it
         qp.hep = 0.5 * e.x;
         qp.hem = 0.5 * e.y;
         qp.inv2sh = (shv > 0.0) ? 1.0 / (2.0 * shv) : 0.0;
@@ -169,10 +169,12 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
 // ---------------------------------------------------------------------------
 // Distance test (Eq. 3).  The canonical FP64 value is
 //   V = 0.5 (ep_u em_w + em_u ep_w) + 2 (sh_u sh_w) d^2,  d = hs_u hc_w - hc_u hs_w,
-// one rounding per operation.  The query-side halves/doubles (0.5 ep_u,
-// 0.5 em_u, 2 sh_u) are exact power-of-two scalings, so
-//   V = (hep_u em_w + hem_u ep_w) + (sh2_u sh_w) d^2
-// rounds to the same bits with two multiplications fewer.
+// one rounding per operation, with sh = 0.5 (ep - em) (sinh r from the
+// table's two exponentials).  The query-side halves (0.5 ep_u, 0.5 em_u) are
+// exact power-of-two scalings, and (ep_w - em_w) rounds to exactly 2 sh_w, so
+// (sh_u (ep_w - em_w)) is exactly 2 (sh_u sh_w) (a doubling is exact) and
+//   V = (hep_u em_w + hem_u ep_w) + (sh_u (ep_w - em_w)) d^2
+// rounds to the same bits, reading no sinh column for the candidate.
 // FP32 filter: with d computed in FP64 and rounded once, every FP32 operand
 // and operation adds at most a relative u32 = 2^-24 to a sum of positive
 // terms, so |V32 - W| <= gamma_8 W and |V64 - W| <= gamma_6(2^-53) W for the
@@ -181,7 +183,7 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
 // Pairs between the two thresholds are decided by V64.
 // ---------------------------------------------------------------------------
 struct Qv {
-    double hep, hem, sh2, hs, hc;
+    double hep, hem, sh, hs, hc;
     float hep32, hem32, sh2_32;
 };
 
@@ -190,7 +192,6 @@ struct Qv {
 struct Cand {
     double2 hw;  // (sin, cos) of theta_w / 2
     double2 ew;  // (exp r_w, exp -r_w)        FP64 form
-    double sh;   // sinh r_w                   FP64 form
     float4 f;    // FP32 shadows               FP32 form
     uint32_t wi; // original index             general model (T > 0)
 };
@@ -210,7 +211,6 @@ __device__ __forceinline__ void load_cand(const Geo &g, uint32_t p, Cand &c) {
     if (SOFT) c.wi = ld<WIDE>(g.idx, p);
     if (!FP32) {
         c.ew = ld<WIDE>(g.epm, p);
-        c.sh = ld<WIDE>(g.sh, p);
     } else {
         c.f = ld<WIDE>(g.f32, p);
     }
@@ -229,7 +229,7 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
     const double d = q.hs * c.hw.y - q.hc * c.hw.x;
     if (!FP32) {
         const double a = q.hep * c.ew.y + q.hem * c.ew.x;
-        const double b = (q.sh2 * c.sh) * (d * d);
+        const double b = (q.sh * (c.ew.x - c.ew.y)) * (d * d);
         return (a + b) < g.K ? 1u : 0u;
     } else {
         const float d32 = (float)d;
@@ -242,7 +242,7 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
         }
         const double2 e = g.epm[p];
         const double a = q.hep * e.y + q.hem * e.x;
-        const double b = (q.sh2 * g.sh[p]) * (d * d);
+        const double b = (q.sh * (e.x - e.y)) * (d * d);
         const uint32_t e64 = (a + b) < g.K ? 1u : 0u;
         uint32_t abl = 0u;
         if (ABL) {
@@ -566,7 +566,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         const double2 h = g.hsc[u.v];
         mine.hep = 0.5 * e.x;
         mine.hem = 0.5 * e.y;
-        mine.sh2 = 2.0 * g.sh[u.v];
+        mine.sh = 0.5 * (e.x - e.y);
         mine.hs = h.x;
         mine.hc = h.y;
         if (SOFT) myqi = g.idx[u.v];
@@ -601,7 +601,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
             S.pb[rk] = pb;
             S.qd[0][rk] = mine.hep;
             S.qd[1][rk] = mine.hem;
-            S.qd[2][rk] = mine.sh2;
+            S.qd[2][rk] = mine.sh;
             S.qd[3][rk] = mine.hs;
             S.qd[4][rk] = mine.hc;
             if (FULL) S.qpos[rk] = u.v;
@@ -630,7 +630,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 Qv q;
                 q.hep = S.qd[0][rk[i]];
                 q.hem = S.qd[1][rk[i]];
-                q.sh2 = S.qd[2][rk[i]];
+                q.sh = S.qd[2][rk[i]];
                 q.hs = S.qd[3][rk[i]];
                 q.hc = S.qd[4][rk[i]];
                 if (FP32) {
@@ -646,7 +646,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                     if (act) {
                         const double d = q.hs * c[i].hw.y - q.hc * c[i].hw.x;
                         const double a = q.hep * c[i].ew.y + q.hem * c[i].ew.x;
-                        const double b = (q.sh2 * c[i].sh) * (d * d);
+                        const double b = (q.sh * (c[i].ew.x - c[i].ew.y)) * (d * d);
                         r = soft_test(g, a + b, S.qi[rk[i]], c[i].wi);
                     }
                 } else {

@@ -6,8 +6,8 @@
 //                  quantisation of the angle; the sort key and the search key
 //   idx[n]    u32  original point index of each sorted position
 //   th[n]            f64 angle
-//   epm[n]           f64x2 (exp(r), exp(-r))
-//   sh[n]            f64 sinh r
+//   epm[n]           f64x2 (exp(r), exp(-r)); the distance test takes sinh r
+//                    as (exp(r) - exp(-r)) / 2 from these two (no column of its own)
 //   hsc[n]           f64x2 (sin(theta/2), cos(theta/2))
 //   f32[n]           f32x4 (exp(r), exp(-r), sinh r, 0) rounded once to FP32
 //   btab[]    u32  per slab j, 2^bits_j + 1 bucket starts over the top bits
@@ -67,8 +67,8 @@ struct Geo {
     uint32_t bto[MAX_BANDS + 1];  // bucket table offset of slab j
     int bshift[MAX_BANDS + 1];    // q >> bshift -> bucket
     const uint32_t *keys, *idx;
-    const double *th, *sh;
-    const double2 *epm;  // (exp(r), exp(-r))
+    const double *th;
+    const double2 *epm;  // (exp(r), exp(-r)); sinh r = (exp(r) - exp(-r)) / 2
     const double2 *hsc;  // (sin(theta/2), cos(theta/2))
     const float4 *f32;   // (exp(r), exp(-r), sinh r, 0) rounded to FP32 (FP32 filter only)
     const uint32_t *btab;
@@ -134,21 +134,23 @@ __device__ __forceinline__ void load_point(const Source &s, uint64_t i, double &
     }
 }
 
-// Per-point values the distance test reads.
+// Per-point values the distance test reads: exp(r), exp(-r), sin(theta/2),
+// cos(theta/2), and sinh r taken as (exp(r) - exp(-r)) / 2 from the first two
+// (one rounded subtraction and an exact halving; a caller table's sinh column
+// is not read).
 __device__ __forceinline__ void point_table(const Source &s, uint64_t i, double theta, double r, double &ep,
                                             double &em, double &sh, double &hs, double &hc) {
     if (s.mode == SRC_TABLE) {
         ep = s.table[i];
         em = s.table[s.n + i];
-        sh = s.table[2 * s.n + i];
         hs = s.table[3 * s.n + i];
         hc = s.table[4 * s.n + i];
     } else {
         ep = exp(r);
         em = exp(-r);
-        sh = sinh(r);
         sincos(theta * 0.5, &hs, &hc);  // one argument reduction for both
     }
+    sh = 0.5 * (ep - em);
 }
 
 // ---- wavefront primitives ------------------------------------------------

@@ -414,14 +414,13 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     // table in sorted order (needs no layout)
     RHG_BUF(th, double, S_TH, n);
     RHG_BUF(epm, double2, S_EP, n);
-    RHG_BUF(sh, double, S_SH, n);
     RHG_BUF(hsc, double2, S_HS, n);
     float4 *f32 = nullptr;
     if (pl.fp32) {
         f32 = (float4 *)c->buf(S_EP32, sizeof(float4) * n);
         if (!f32) return RHG_ENOMEM;
     }
-    rhgk::gather(src, vals, n, th, epm, sh, hsc, f32, st);
+    rhgk::gather(src, vals, n, th, epm, hsc, f32, st);
     const bool update = rq.moved != nullptr;
     uint32_t *msorted = nullptr, *morig = nullptr;
     if (update) {
@@ -469,7 +468,6 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.idx = vals;
     g.th = th;
     g.epm = epm;
-    g.sh = sh;
     g.hsc = hsc;
     g.f32 = f32;
     g.btab = btab;

@@ -228,7 +228,6 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         sA.geo.keys = D.keys;
         sA.geo.idx = D.vals;
         sA.geo.th = D.th;
-        sA.geo.sh = D.sh;
         sA.geo.epm = D.epm;
         sA.geo.hsc = D.hsc;
         sA.geo.f32 = D.f32;
@@ -251,7 +250,6 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         point_table(D.src, v, th, r, a, b, c, d, e);
         D.th[s] = th;
         D.epm[s] = make_double2(a, b);
-        D.sh[s] = c;
         D.hsc[s] = make_double2(d, e);
         if (D.f32) D.f32[s] = make_float4((float)a, (float)b, (float)c, 0.0f);
     }
@@ -387,7 +385,7 @@ SmallLayout small_layout_units(uint64_t n, int B, uint64_t unit_cap, bool fp32) 
     L.btab_cap = n + 2ull * B + 8;
     uint64_t b = 0;
     b += 4 * align256(4 * n);                          // keys, vals, keys2, vals2
-    b += 2 * align256(8 * n) + 2 * align256(16 * n);   // th, sh, epm, hsc
+    b += align256(8 * n) + 2 * align256(16 * n);       // th, epm, hsc
     if (fp32) b += align256(16 * n);                   // f32
     b += align256(4 * L.btab_cap) + align256(8 * L.win_cap);
     b += 2 * align256(8 * nb) + 2 * align256(8 * (nb + 1)) + align256(8 * nb * (uint64_t)(B + 1));
@@ -420,7 +418,6 @@ void small_fill_desc(rhgk::SmallDesc &D, const Plan &pl, const Request &rq, cons
     D.keys2 = (uint32_t *)take(4 * n);
     D.vals2 = (uint32_t *)take(4 * n);
     D.th = (double *)take(8 * n);
-    D.sh = (double *)take(8 * n);
     D.epm = (double2 *)take(16 * n);
     D.hsc = (double2 *)take(16 * n);
     D.f32 = pl.fp32 ? (float4 *)take(16 * n) : nullptr;

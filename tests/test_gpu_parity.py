@@ -145,8 +145,9 @@ def test_seeded_points_match_oracle_sampler(ctx, orc, n, alpha, kbar, seed):
     same = r == ro                                     # compare tables where the radii agree bitwise
     assert same.mean() > 0.5
     to = orc.table(tho, ro)
-    assert _ulps(t[:, same], to[:, same]).max() <= 2
+    assert _ulps(t[:2, same], to[:2, same]).max() <= 2  # exp(r), exp(-r)
     assert _ulps(t[3:], to[3:]).max() <= 2             # angle entries: same angles everywhere
+    assert np.array_equal(t[2], 0.5 * (t[0] - t[1]))   # sinh r from the two exponentials
     assert K == math.cosh(R)
 
 

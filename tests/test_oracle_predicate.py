@@ -7,8 +7,9 @@ It is pinned here against things other than itself:
   r_u + r_v; a point at the origin is at distance r_other from everything;
 * the literal Eq. 3 evaluated from (theta, r) in 60-digit arithmetic, within
   an error bound derived from the FP64 rounding of the table and the
-  operations (relative 16u plus the effect of an absolute 8u error in the
-  half-angle sine);
+  operations (relative 16u, the effect of an absolute 8u error in the
+  half-angle sine, and of the absolute 3u cosh r error of sinh r taken as
+  (e^r - e^-r) / 2), also for points near the centre;
 * exact symmetry in (u, v), which the outward-only scan relies on.
 """
 import math
@@ -34,7 +35,12 @@ def error_bound(tab, u, v, V):
     sh = tab[2]
     d = tab[3][u] * tab[4][v] - tab[4][u] * tab[3][v]
     ad = 8 * U
-    return 16 * U * V + 2 * sh[u] * sh[v] * (2 * abs(d) * ad + ad * ad)
+    # sinh r is (e^r - e^-r) / 2 of the table's exponentials: an absolute
+    # error of at most 3 u cosh r each (cosh r = (e^r + e^-r) / 2), which
+    # enters through 2 sinh r_u sinh r_v sin^2
+    ch = 0.5 * (tab[0] + tab[1])
+    dsh = 2 * d * d * 3 * U * 1.01 * (ch[u] * sh[v] + sh[u] * ch[v])
+    return 16 * U * V + 2 * sh[u] * sh[v] * (2 * abs(d) * ad + ad * ad) + dsh
 
 
 def test_closed_forms(orc):
@@ -79,6 +85,21 @@ def test_against_high_precision(orc, R):
         assert err <= error_bound(t, u, v, V), (u, v, V, float(ex))
         if abs(ex - K) > error_bound(t, u, v, V):
             assert orc.is_edge(t, u, v, K) == bool(ex < K)
+
+
+def test_small_radii_against_high_precision(orc):
+    # sinh r from e^r - e^-r cancels for small r: pairs of a point near the
+    # centre and one anywhere, at every angle, stay within the bound
+    g = np.random.default_rng(9)
+    n = 200
+    r = np.concatenate([10.0 ** g.uniform(-9, -1, n // 2), g.random(n // 2) * 20])
+    th = g.random(n) * 2 * np.pi
+    t = _tab(orc, th, r)
+    for u in range(n // 2):
+        for v in (n // 2 + u, (u + 1) % (n // 2)):
+            V = orc.coshdist(t, u, v)
+            ex = exact_cosh_dist(th[u], r[u], th[v], r[v])
+            assert abs(mpmath.mpf(V) - ex) <= error_bound(t, u, v, V), (u, v, r[u], r[v])
 
 
 def test_symmetry_bitwise(orc):

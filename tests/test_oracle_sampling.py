@@ -69,11 +69,19 @@ def test_table_accuracy(orc):
     th = np.concatenate([th, [0.0, 2 * np.pi, 1e-300, np.pi]])
     r = np.concatenate([r, [0.0, 26.5, 1e-12, 13.0]])
     t = orc.table(th, r)
-    worst = 0.0
+    worst, worst_sh = 0.0, 0.0
     for i in range(len(th)):
         R_ = mpmath.mpf(float(r[i]))
         T_ = mpmath.mpf(float(th[i])) / 2
         refs = [mpmath.exp(R_), mpmath.exp(-R_), mpmath.sinh(R_), mpmath.sin(T_), mpmath.cos(T_)]
-        for k in range(5):
+        for k in (0, 1, 3, 4):
             worst = max(worst, float(_ulps(t[k, i], refs[k])))
+        # sinh r is (e^r - e^-r) / 2 of the two exponentials: its error is
+        # absolute, within 3 u cosh r (2 ulp in each exponential plus the
+        # rounded subtraction), and relative to sinh r once r is not small
+        err = abs(mpmath.mpf(float(t[2, i])) - refs[2])
+        worst_sh = max(worst_sh, float(err / (mpmath.cosh(R_) * mpmath.mpf(2) ** -53)))
+        if float(r[i]) >= 1.0:
+            worst = max(worst, float(_ulps(t[2, i], refs[2])) / 2)  # within 4 ulp of sinh r
     assert worst <= 2.0, worst
+    assert worst_sh <= 3.0, worst_sh
