@@ -361,7 +361,7 @@ void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t
 // re-sampled (seeded mode) or read, its table computed or copied.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gather(Source src, const uint32_t *idx, uint32_t n, double *th,
-                                                double2 *epm, double2 *hsc, float4 *f32) {
+                                                double2 *epm, double2 *hsc, float2 *f32) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     uint32_t v = idx[s];
@@ -371,11 +371,11 @@ __global__ __launch_bounds__(256) void k_gather(Source src, const uint32_t *idx,
     th[s] = t;
     epm[s] = make_double2(a, b);
     hsc[s] = make_double2(d, e);
-    if (f32) f32[s] = make_float4((float)a, (float)b, (float)c, 0.0f);
+    if (f32) f32[s] = make_float2((float)a, (float)b);
 }
 
 void gather(const Source &src, const uint32_t *idx, uint64_t n, double *th, double2 *epm, double2 *hsc,
-            float4 *f32, hipStream_t st) {
+            float2 *f32, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, idx, (uint32_t)n, th,
                        epm, hsc, f32);

@@ -175,16 +175,23 @@ __device__ __forceinline__ void plan_batch(const Geo &g, uint2 *win, uint64_t *b
 // (sh_u (ep_w - em_w)) is exactly 2 (sh_u sh_w) (a doubling is exact) and
 //   V = (hep_u em_w + hem_u ep_w) + (sh_u (ep_w - em_w)) d^2
 // rounds to the same bits, reading no sinh column for the candidate.
-// FP32 filter: with d computed in FP64 and rounded once, every FP32 operand
-// and operation adds at most a relative u32 = 2^-24 to a sum of positive
-// terms, so |V32 - W| <= gamma_8 W and |V64 - W| <= gamma_6(2^-53) W for the
-// exact W of the table values; with mu = 2^-20 > gamma_8 + gamma_6,
+// FP32 filter, from the FP64 d rounded once and 8-byte shadows (e^r, e^-r in
+// FP32) per candidate:
+//   V32 = (0.5 ep32_u) em32_w + (0.5 em32_u) ep32_w + (sh32_u d32)(t32_w d32),
+//   t32_w = ep32_w - em32_w  (2 sinh r_w, from the shadows).
+// Against the exact W of the FP64 table values (a + sh_u t_w d^2, t_w =
+// ep_w - em_w), every FP32 operand and product adds at most a relative
+// u32 = 2^-24 to sums of positive terms (gamma_8 in all), and the
+// subtraction adds an absolute error of at most u32 (ep_w + em_w)(1 + u32),
+// which through sh_u d^2 is at most u32 (1 + u32)(b + 2 ep_u em_w / 2) <=
+// 2 u32 (1 + u32) W.  So |V32 - W| <= (gamma_8 + 2.1 u32) W < 6e-7 W, and
+// |V64 - W| <= gamma_6(2^-53) W; with mu = 2^-20 (9.5e-7) above their sum,
 // V32 <= RD(K(1-mu)) implies V64 < K and V32 >= RU(K(1+mu)) implies V64 >= K.
 // Pairs between the two thresholds are decided by V64.
 // ---------------------------------------------------------------------------
 struct Qv {
     double hep, hem, sh, hs, hc;
-    float hep32, hem32, sh2_32;
+    float hep32, hem32, sh32;
 };
 
 // Candidate operands, loaded for several candidates before any is decided so
@@ -192,7 +199,7 @@ struct Qv {
 struct Cand {
     double2 hw;  // (sin, cos) of theta_w / 2
     double2 ew;  // (exp r_w, exp -r_w)        FP64 form
-    float4 f;    // FP32 shadows               FP32 form
+    float2 f;    // FP32 (exp r_w, exp -r_w)   FP32 form
     uint32_t wi; // original index             general model (T > 0)
 };
 
@@ -234,7 +241,8 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
     } else {
         const float d32 = (float)d;
         const float a32 = q.hep32 * c.f.y + q.hem32 * c.f.x;
-        const float b32 = (q.sh2_32 * d32) * (c.f.z * d32);
+        const float t32 = c.f.x - c.f.y;
+        const float b32 = (q.sh32 * d32) * (t32 * d32);
         const float v32 = a32 + b32;
         const bool sure_in = v32 <= g.klo32, sure_out = v32 >= g.khi32;
         if (sure_in || sure_out) {
@@ -246,11 +254,11 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
         const uint32_t e64 = (a + b) < g.K ? 1u : 0u;
         uint32_t abl = 0u;
         if (ABL) {
-            const float chu = q.hep32 + q.hem32, shu = 0.5f * q.sh2_32;
-            const float chw = 0.5f * (c.f.x + c.f.y);
+            const float chu = q.hep32 + q.hem32, shu = q.sh32;
+            const float chw = 0.5f * (c.f.x + c.f.y), shw = (float)(0.5 * (e.x - e.y));
             const float cu = (float)(q.hc * q.hc - q.hs * q.hs), su = (float)(2.0 * (q.hs * q.hc));
             const float cw = (float)(c.hw.y * c.hw.y - c.hw.x * c.hw.x), sw = (float)(2.0 * (c.hw.x * c.hw.y));
-            const float A = chu * chw, S = shu * c.f.z;
+            const float A = chu * chw, S = shu * shw;
             const float C = cu * cw + su * sw;
             const float V = A - S * C;
             const float K32 = (float)g.K;
@@ -571,10 +579,10 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
         mine.hc = h.y;
         if (SOFT) myqi = g.idx[u.v];
         if (FP32) {
-            const float4 f = g.f32[u.v];
+            const float2 f = g.f32[u.v];
             mine.hep32 = 0.5f * f.x;
             mine.hem32 = 0.5f * f.y;
-            mine.sh2_32 = 2.0f * f.z;
+            mine.sh32 = (float)mine.sh;
         }
     }
 #pragma unroll
@@ -609,7 +617,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
             if (FP32) {
                 S.qf[0][rk] = mine.hep32;
                 S.qf[1][rk] = mine.hem32;
-                S.qf[2][rk] = mine.sh2_32;
+                S.qf[2][rk] = mine.sh32;
             }
         }
         uint32_t base = (uint32_t)__popcll(__ballot(ne && relu == BEFORE_UNIT));
@@ -636,7 +644,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 if (FP32) {
                     q.hep32 = S.qf[0][rk[i]];
                     q.hem32 = S.qf[1][rk[i]];
-                    q.sh2_32 = S.qf[2][rk[i]];
+                    q.sh32 = S.qf[2][rk[i]];
                 }
                 // FP32 filter: test every lane and mask (the loads issue together);
                 // FP64: lanes past the end skip the test (measured faster there)

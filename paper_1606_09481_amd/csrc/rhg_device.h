@@ -9,7 +9,7 @@
 //   epm[n]           f64x2 (exp(r), exp(-r)); the distance test takes sinh r
 //                    as (exp(r) - exp(-r)) / 2 from these two (no column of its own)
 //   hsc[n]           f64x2 (sin(theta/2), cos(theta/2))
-//   f32[n]           f32x4 (exp(r), exp(-r), sinh r, 0) rounded once to FP32
+//   f32[n]           f32x2 (exp(r), exp(-r)) rounded once to FP32
 //   btab[]    u32  per slab j, 2^bits_j + 1 bucket starts over the top bits
 //                  of q (a direct-mapped index into the sorted slab)
 //   win[]     uint2 per (query, slab j >= slab(query)): circular position
@@ -70,7 +70,7 @@ struct Geo {
     const double *th;
     const double2 *epm;  // (exp(r), exp(-r)); sinh r = (exp(r) - exp(-r)) / 2
     const double2 *hsc;  // (sin(theta/2), cos(theta/2))
-    const float4 *f32;   // (exp(r), exp(-r), sinh r, 0) rounded to FP32 (FP32 filter only)
+    const float2 *f32;   // (exp(r), exp(-r)) rounded to FP32 (FP32 filter only)
     const uint32_t *btab;
     // Update mode (re-query after a move), else null: bit s % 32 of word
     // s / 32 is set for the points that moved, in sorted order.  Only moved

@@ -43,7 +43,7 @@ void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t
 // a1 + a3 gather: per sorted position, the point's angle and table
 // (computed, or copied from the caller's table) in sorted order.
 void gather(const rhgd::Source &src, const uint32_t *idx, uint64_t n, double *th, double2 *epm,
-            double2 *hsc, float4 *f32, hipStream_t st);
+            double2 *hsc, float2 *f32, hipStream_t st);
 
 // Same values in original order (for exporting the exact bits used).
 void point_values(const rhgd::Source &src, uint64_t n, double *th, double *rr, double *table5xn, hipStream_t st);
@@ -146,7 +146,7 @@ struct SmallDesc {
     uint32_t *keys, *vals, *keys2, *vals2;
     double *th;
     double2 *epm, *hsc;
-    float4 *f32;
+    float2 *f32;
     uint32_t *btab;
     uint64_t btab_cap;
     uint2 *win;

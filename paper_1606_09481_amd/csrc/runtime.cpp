@@ -415,9 +415,9 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     RHG_BUF(th, double, S_TH, n);
     RHG_BUF(epm, double2, S_EP, n);
     RHG_BUF(hsc, double2, S_HS, n);
-    float4 *f32 = nullptr;
+    float2 *f32 = nullptr;
     if (pl.fp32) {
-        f32 = (float4 *)c->buf(S_EP32, sizeof(float4) * n);
+        f32 = (float2 *)c->buf(S_EP32, sizeof(float2) * n);
         if (!f32) return RHG_ENOMEM;
     }
     rhgk::gather(src, vals, n, th, epm, hsc, f32, st);

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         D.th[s] = th;
         D.epm[s] = make_double2(a, b);
         D.hsc[s] = make_double2(d, e);
-        if (D.f32) D.f32[s] = make_float4((float)a, (float)b, (float)c, 0.0f);
+        if (D.f32) D.f32[s] = make_float2((float)a, (float)b);
     }
     __syncthreads();
 
@@ -386,7 +386,7 @@ SmallLayout small_layout_units(uint64_t n, int B, uint64_t unit_cap, bool fp32) 
     uint64_t b = 0;
     b += 4 * align256(4 * n);                          // keys, vals, keys2, vals2
     b += align256(8 * n) + 2 * align256(16 * n);       // th, epm, hsc
-    if (fp32) b += align256(16 * n);                   // f32
+    if (fp32) b += align256(8 * n);                    // f32
     b += align256(4 * L.btab_cap) + align256(8 * L.win_cap);
     b += 2 * align256(8 * nb) + 2 * align256(8 * (nb + 1)) + align256(8 * nb * (uint64_t)(B + 1));
     b += 2 * align256(4 * L.unit_cap) + align256(8 * (L.unit_cap + 1)) + align256(8 * L.unit_cap * BITMAP_WORDS);
@@ -420,7 +420,7 @@ void small_fill_desc(rhgk::SmallDesc &D, const Plan &pl, const Request &rq, cons
     D.th = (double *)take(8 * n);
     D.epm = (double2 *)take(16 * n);
     D.hsc = (double2 *)take(16 * n);
-    D.f32 = pl.fp32 ? (float4 *)take(16 * n) : nullptr;
+    D.f32 = pl.fp32 ? (float2 *)take(8 * n) : nullptr;
     D.btab_cap = lay.btab_cap;
     D.btab = (uint32_t *)take(4 * D.btab_cap);
     D.win_cap = lay.win_cap;
