@@ -20,19 +20,22 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rhg_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# RHG_ORACLE_LIB: another build of rhg_oracle.c to load instead (the mutation
+# test loads builds with planted mistakes and requires a pin to fail)
+_BUILT = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("RHG_ORACLE_LIB") or _BUILT
 
 TWO_PI = 2.0 * np.pi  # fl(2*pi), the sampler's angle period
 
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
+    if force or not os.path.exists(_BUILT):
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-pthread", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-pthread", "-o", _BUILT + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(_BUILT + ".tmp", _BUILT)
+    return _BUILT
 
 
 _lib = None
