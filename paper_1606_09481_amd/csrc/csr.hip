@@ -1,9 +1,10 @@
 // csr.hip -- symmetric CSR adjacency of an edge list: row v holds every w
-// with (v, w) or (w, v) in the list.  Each pair becomes two directed entries
-// (row, neighbour); a stable LSD radix sort by row (the sort of the slab
-// keys) orders them, so within a row the neighbours keep the order of the
-// pairs in the list; the row pointers are the first entry of each row in the
-// sorted rows.
+// with (v, w) or (w, v) in the list.  Each pair (x, y) stands for two
+// directed entries (row, neighbour), (x, y) then (y, x); a stable LSD radix
+// sort by row (the sort of the slab keys, whose first pass reads the pairs
+// and expands them) orders them, so within a row the neighbours keep the
+// order of the pairs in the list; the row pointers are the first entry of
+// each row in the sorted rows.
 #include <algorithm>
 
 #include "rhg_kernels.h"
@@ -11,16 +12,15 @@
 namespace rhgk {
 using namespace rhgd;
 
-// Entries 2e and 2e + 1 of pair e: (lo, hi) and (hi, lo).  An end outside
-// 0..n-1 raises *err (the caller stops before sorting) and is written as 0,
-// so no later step indexes outside row_ptr.  The row digits of every sort
-// pass are counted on the way (the sort then needs no counting read of its
-// own): LDS histograms in 8 copies, lane l counting into copy l mod 8, since
-// a query's row repeats over runs of pairs and would otherwise put the lanes
-// of an LDS atomic on one bin; one global add per bin and workgroup.
+// The rows of the entries of pair e are its two ends.  An end outside 0..n-1
+// raises *err (the caller stops before sorting).  The row digits of every
+// sort pass are counted here, one read of the pairs: LDS histograms in 8
+// copies, lane l counting into copy l mod 8, since a query's row repeats over
+// runs of pairs and would otherwise put the lanes of an LDS atomic on one
+// bin; one global add per bin and workgroup.
 constexpr int DIR_COPIES = 8;
-__global__ __launch_bounds__(256) void k_directed(const int2 *pairs, uint64_t m, uint32_t n, uint2 *rows,
-                                                  uint2 *nbrs, uint32_t *err, int passes, uint32_t *counts) {
+__global__ __launch_bounds__(256) void k_directed_counts(const int2 *pairs, uint64_t m, uint32_t n, uint32_t *err,
+                                                         int passes, uint32_t *counts) {
     __shared__ uint32_t h[DIR_COPIES][4][256];
     const int c = threadIdx.x & (DIR_COPIES - 1);
     for (int q = 0; q < 4; ++q)
@@ -34,8 +34,6 @@ __global__ __launch_bounds__(256) void k_directed(const int2 *pairs, uint64_t m,
             bad = true;
             a = b = 0u;
         }
-        rows[e] = make_uint2(a, b);
-        nbrs[e] = make_uint2(b, a);
         for (int q = 0; q < passes; ++q) {
             atomicAdd(&h[c][q][(a >> (8 * q)) & 255u], 1u);
             atomicAdd(&h[c][q][(b >> (8 * q)) & 255u], 1u);
@@ -50,12 +48,11 @@ __global__ __launch_bounds__(256) void k_directed(const int2 *pairs, uint64_t m,
     }
 }
 
-void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err, int passes,
-              uint32_t *counts, hipStream_t st) {
+void directed_counts(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *err, int passes, uint32_t *counts,
+                     hipStream_t st) {
     if (!m) return;
     const unsigned blocks = (unsigned)std::min<uint64_t>(2048, (m + 255) / 256);
-    hipLaunchKernelGGL(k_directed, dim3(blocks), dim3(256), 0, st, pairs, m, (uint32_t)n, (uint2 *)rows, (uint2 *)nbrs,
-                       err, passes, counts);
+    hipLaunchKernelGGL(k_directed_counts, dim3(blocks), dim3(256), 0, st, pairs, m, (uint32_t)n, err, passes, counts);
 }
 
 // row_ptr[v] = first sorted entry with row >= v, v = 0..n: entry i writes the

@@ -186,6 +186,10 @@ __device__ __forceinline__ uint32_t block_excl_256(uint32_t x, uint32_t *wtot) {
     return before + incl - x;
 }
 
+// PAIRS: the input is a list of n/2 pairs (x, y) read as the n entries
+// (x, y), (y, x) of each pair in turn (key, value): the directed entries of
+// a CSR, expanded on the way in.
+template <bool PAIRS>
 __global__ __launch_bounds__(S_THREADS) void k_sort_pass(const uint32_t *keys, const uint32_t *vals,
                                                          uint32_t *keys_out, uint32_t *vals_out, uint32_t n,
                                                          int shift, const uint32_t *counts, uint64_t *status,
@@ -206,8 +210,15 @@ __global__ __launch_bounds__(S_THREADS) void k_sort_pass(const uint32_t *keys, c
     for (int i = 0; i < S_ITEMS; ++i) {
         const uint32_t p = base + i * 64 + l;
         const bool ok = p < n;
-        k[i] = ok ? keys[p] : 0u;
-        v[i] = ok ? vals[p] : 0u;
+        if (PAIRS) {
+            // lanes 2k and 2k + 1 read the same pair: one coalesced 8-byte load each
+            const uint2 q = ok ? ((const uint2 *)keys)[p >> 1] : make_uint2(0u, 0u);
+            k[i] = (p & 1u) ? q.y : q.x;
+            v[i] = (p & 1u) ? q.x : q.y;
+        } else {
+            k[i] = ok ? keys[p] : 0u;
+            v[i] = ok ? vals[p] : 0u;
+        }
     }
     // stable rank per wavefront and digit
 #pragma unroll
@@ -345,7 +356,7 @@ void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t
     const SortScratch x = sort_scratch(scratch, ntiles);
     uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_sort_pass, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, 8 * p,
+        hipLaunchKernelGGL(k_sort_pass<false>, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, 8 * p,
                            x.counts + p * 256, x.status + (size_t)p * ntiles * 256, x.tickets + p, x.error);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
@@ -353,6 +364,25 @@ void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t
     if (ka != keys && copy_back) {
         (void)hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    }
+}
+
+void sort_pairs_by_counts(const int2 *pairs, uint64_t n, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp,
+                          uint32_t *vals_tmp, void *scratch, int bits, hipStream_t st) {
+    if (n == 0) return;
+    const uint32_t ntiles = (uint32_t)((n + S_TILE - 1) / S_TILE);
+    const int passes = sort_passes(bits);
+    const SortScratch x = sort_scratch(scratch, ntiles);
+    // the last pass must write (keys, vals): passes alternate from there back
+    uint32_t *ka = passes % 2 ? keys : keys_tmp, *va = passes % 2 ? vals : vals_tmp;
+    uint32_t *kb = passes % 2 ? keys_tmp : keys, *vb = passes % 2 ? vals_tmp : vals;
+    hipLaunchKernelGGL(k_sort_pass<true>, dim3(ntiles), dim3(S_THREADS), 0, st, (const uint32_t *)pairs, nullptr, ka,
+                       va, (uint32_t)n, 0, x.counts, x.status, x.tickets, x.error);
+    for (int p = 1; p < passes; ++p) {
+        hipLaunchKernelGGL(k_sort_pass<false>, dim3(ntiles), dim3(S_THREADS), 0, st, ka, va, kb, vb, (uint32_t)n, 8 * p,
+                           x.counts + p * 256, x.status + (size_t)p * ntiles * 256, x.tickets + p, x.error);
+        uint32_t *t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
     }
 }
 

@@ -39,6 +39,11 @@ void sort_prepare(void *scratch, uint64_t n, int bits, hipStream_t st);
 uint32_t *sort_counts(void *scratch);
 void sort_by_counts(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, void *scratch, uint64_t n,
                     int bits, hipStream_t st, bool copy_back = true);
+// The same for the n entries (x, y), (y, x) of n/2 pairs (n even), read from
+// the pairs by the first pass: sorted entries end in (keys, vals); the
+// *_tmp buffers, and keys and vals themselves, serve the passes in between.
+void sort_pairs_by_counts(const int2 *pairs, uint64_t n, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp,
+                          uint32_t *vals_tmp, void *scratch, int bits, hipStream_t st);
 
 // a1 + a3 gather: per sorted position, the point's angle and table
 // (computed, or copied from the caller's table) in sorted order.
@@ -75,12 +80,12 @@ void move(uint64_t n, double alpha, double R, double S, double *theta, double *r
 // of the list (keep_tiles(m) tiles; *err set for an end outside 0..n-1) and
 // written in their order at out[offs[tile] ..].
 uint64_t moved_bit_words(uint64_t n);
-// CSR: the 2m directed entries of m pairs (rows[2e..2e+1] = lo, hi; nbrs the
-// other ends; *err set for an end outside 0..n-1, written as 0), their row
-// digits added to the sort's counts (`passes` passes), and the row pointers
-// row_ptr[0..n] of rows sorted by row (len entries, rows < n).
-void directed(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *rows, uint32_t *nbrs, uint32_t *err, int passes,
-              uint32_t *counts, hipStream_t st);
+// CSR: the row digits of the 2m directed entries of m pairs (both ends of
+// every pair) added to the sort's counts (`passes` passes), *err set for an
+// end outside 0..n-1; and the row pointers row_ptr[0..n] of rows sorted by
+// row (len entries, rows < n).
+void directed_counts(const int2 *pairs, uint64_t m, uint64_t n, uint32_t *err, int passes, uint32_t *counts,
+                     hipStream_t st);
 void row_pointers(const uint32_t *rows, uint64_t len, uint64_t n, uint64_t *row_ptr, hipStream_t st);
 void moved_bits(const uint32_t *idx, const uint8_t *moved, uint64_t n, uint32_t *out, hipStream_t st);
 uint64_t keep_tiles(uint64_t m);

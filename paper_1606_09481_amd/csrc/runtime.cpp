@@ -835,24 +835,18 @@ extern "C" rhg_status rhg_csr_from_pairs(rhg_ctx *ctx, uint64_t n, const int32_t
         uint32_t *err = (uint32_t *)c->buf(S_CSRERR, sizeof(uint32_t));
         void *scr = c->buf(S_CSRSCR, rhgk::sort_scratch_bytes(len));
         if (!rows || !rows2 || !nbrs2 || !err || !scr) return RHG_ENOMEM;
-        // the sorted entries must end in (rows, col): with an odd number of
-        // passes they start in the other buffers, so no copy back is needed;
-        // with an even number the neighbours start in nbrs2 too (col is not
-        // written before the ends are checked) and end there, copied to col
+        // the ends are checked (and the sort's digits counted) before any
+        // sort pass writes: col is untouched when they are rejected
         const int bits = std::max(1, ceil_log2(n));
-        const bool odd = rhgk::sort_passes(bits) % 2 == 1;
-        uint32_t *r0 = odd ? rows2 : rows, *c0 = nbrs2;
-        uint32_t *r1 = odd ? rows : rows2, *c1 = (uint32_t *)col;
         RHG_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), st));
-        rhgk::sort_prepare(scr, len, bits, st);  // the expansion adds the sort's digit counts
-        rhgk::directed((const int2 *)pairs, m, n, r0, c0, err, rhgk::sort_passes(bits), rhgk::sort_counts(scr), st);
+        rhgk::sort_prepare(scr, len, bits, st);
+        rhgk::directed_counts((const int2 *)pairs, m, n, err, rhgk::sort_passes(bits), rhgk::sort_counts(scr), st);
         uint32_t *err_host = (uint32_t *)((char *)c->pinned + 1036);
         RHG_HIP(hipMemcpyAsync(err_host, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         RHG_HIP(hipStreamSynchronize(st));
         if (*err_host != 0) return RHG_EINVAL;  // an end outside 0..n-1: nothing sorted or written
         // stable by row: a row's neighbours keep the order of their pairs
-        rhgk::sort_by_counts(r0, c0, r1, c1, scr, len, bits, st, false);
-        if (!odd) RHG_HIP(hipMemcpyAsync(col, nbrs2, sizeof(uint32_t) * len, hipMemcpyDeviceToDevice, st));
+        rhgk::sort_pairs_by_counts((const int2 *)pairs, len, rows, (uint32_t *)col, rows2, nbrs2, scr, bits, st);
         RHG_HIP(hipMemcpyAsync(err_host, rhgk::sort_error_flag(scr), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     }
     rhgk::row_pointers(rows, len, n, row_ptr, st);
