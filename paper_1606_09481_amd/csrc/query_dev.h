@@ -280,13 +280,17 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
 // transcendental, U in [2^-(j+1), 2^-j) (j from the leading zeros of k)
 // needs f > 2^-(j+1), which needs V < lev[j+1] (with a margin far above the
 // rounding of f); most candidates stop there, so exp and acosh run for few.
-__device__ __forceinline__ uint32_t soft_test(const Geo &g, double V, uint32_t qi, uint32_t wi) {
-    if (!(V < g.K)) return 0u;
+// soft_pre is that first part: true (with U) when the exact test must decide.
+__device__ __forceinline__ bool soft_pre(const Geo &g, double V, uint32_t qi, uint32_t wi, double &U) {
+    if (!(V < g.K)) return false;
     const uint32_t lo = qi < wi ? qi : wi, hi = qi < wi ? wi : qi;
     const uint64_t k = pair_k(g.pseed, lo, hi);
     const int j = __clzll((long long)k) - 11;  // U in [2^-(j+1), 2^-j); j = -1 for U = 1
-    if (j < 0 || !(V < g.lev[j + 1])) return 0u;
-    const double U = (double)k * 0x1p-53;
+    if (j < 0 || !(V < g.lev[j + 1])) return false;
+    U = (double)k * 0x1p-53;
+    return true;
+}
+__device__ __forceinline__ uint32_t soft_exact(const Geo &g, double V, double U) {
     const double x = V > 1.0 ? acosh(V) : 0.0;
     const double y = (x - g.R) / g.t2;
     const double f = 1.0 / (1.0 + exp(y));
@@ -524,6 +528,7 @@ __device__ __forceinline__ uint32_t position_pb(uint32_t pb, uint32_t t, uint32_
 // Per-wavefront LDS of the count pass.
 // (FP32 operands only in the filter form, to keep the FP64 form's LDS, and
 // with it the workgroups per CU, down.)
+constexpr uint32_t SOFT_Q = 128;
 template <int FP32, bool FULL = false, bool SOFT = false>
 struct CountSmem {
     uint32_t pb[64];    // per rank: start position - flattened offset
@@ -534,7 +539,28 @@ struct CountSmem {
     uint2 wpre[SEG_PRE][64];
     uint32_t qpos[FULL ? 64 : 1];  // per rank: the query's sorted position (update mode)
     uint32_t qi[SOFT ? 64 : 1];    // per rank: the query's original index (general model)
+    // general model: candidates waiting for the exact test (a ring of
+    // SOFT_Q): V, U and the candidate's bit in the unit's bitmap
+    double sv[SOFT ? SOFT_Q : 1], su[SOFT ? SOFT_Q : 1];
+    uint32_t sp[SOFT ? SOFT_Q : 1];
 };
+
+// General model: the exact test of the first n (<= 64) queued candidates,
+// lane l taking entry head + l; an edge sets its bit in the unit's bitmap
+// (after that round's word was written).  Returns the edges found.
+template <int FP32, bool FULL>
+__device__ __forceinline__ uint32_t soft_drain(const Geo &g, CountSmem<FP32, FULL, true> &S, uint32_t head,
+                                               uint32_t n, int lane) {
+    wave_lds_sync();
+    const uint32_t k = (head + (uint32_t)lane) & (SOFT_Q - 1);
+    const bool mine = (uint32_t)lane < n;
+    const uint32_t e = mine ? soft_exact(g, S.sv[k], S.su[k]) : 0u;
+    const uint32_t pos = S.sp[k];
+    if (e) atomicOr(&S.bits[pos >> 6], 1ull << (pos & 63u));
+    const uint32_t got = (uint32_t)__popcll(__ballot(e != 0u));
+    wave_lds_sync();
+    return got;
+}
 
 // Ranks and positions of one count step (VT x 64 candidates from t0): the
 // rank of each candidate's window and its position in the slab; lanes at or
@@ -559,7 +585,8 @@ __device__ __forceinline__ void count_positions(uint8_t *flags, const uint32_t *
 // FULL: update mode (Geo::moved): a candidate that passes the distance test
 // is an edge unless it is the query itself, or a moved point that comes
 // before the query in sorted order (that pair is the other query's).
-// SOFT: the general model (FP64 only), each candidate decided by soft_test.
+// SOFT: the general model (FP64 only), each candidate decided by soft_pre and,
+// queued, soft_exact.
 // ABL: the FP32 form with the literal-Eq. 3 ablation counters (edge_test).
 template <int FP32, bool WIDE, bool FULL = false, bool SOFT = false, bool ABL = false>
 __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, uint64_t slot, int lane,
@@ -592,6 +619,7 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
     prefetch_windows(A, u, lane, S.wpre);
     uint32_t word = 0;     // next free bitmap word
     uint32_t found = 0, rechecks = 0, disagree = 0, lit_und = 0, lit_wrong = 0;
+    uint32_t sq_head = 0, sq_n = 0;  // general model: the queue of exact tests (uniform)
     uint32_t segs = u.segmask;
     for (int seg = 0; segs != 0u; ++seg) {
         const int bit = __builtin_ctz(segs);
@@ -650,13 +678,26 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 // FP64: lanes past the end skip the test (measured faster there)
                 uint32_t r;
                 if (SOFT) {
+                    // no candidate is decided here: those past the level test
+                    // queue for the exact one, which sets their bits later
                     r = 0u;
+                    double V = 0.0, U = 0.0;
+                    bool need = false;
                     if (act) {
                         const double d = q.hs * c[i].hw.y - q.hc * c[i].hw.x;
                         const double a = q.hep * c[i].ew.y + q.hem * c[i].ew.x;
                         const double b = (q.sh * (c[i].ew.x - c[i].ew.y)) * (d * d);
-                        r = soft_test(g, a + b, S.qi[rk[i]], c[i].wi);
+                        V = a + b;
+                        need = soft_pre(g, V, S.qi[rk[i]], c[i].wi, U);
                     }
+                    const uint64_t nm = __ballot(need);
+                    if (need) {
+                        const uint32_t k = (sq_head + sq_n + (uint32_t)__popcll(nm & lt)) & (SOFT_Q - 1);
+                        S.sv[k] = V;
+                        S.su[k] = U;
+                        S.sp[k] = (word + i) * 64u + (uint32_t)lane;
+                    }
+                    sq_n += (uint32_t)__popcll(nm);
                 } else {
                     r = FP32 ? (edge_test<FP32, ABL>(g, q, c[i], p[i], A.exhaustive) & (act ? 31u : 0u))
                              : (act ? edge_test<FP32>(g, q, c[i], p[i], A.exhaustive) : 0u);
@@ -677,6 +718,13 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 const uint64_t m = __ballot(flag);
                 found += (uint32_t)__popcll(m);
                 if (t0 + 64u * i < e && lane == 0) S.bits[word + i] = m;
+                if constexpr (SOFT) {
+                    if (sq_n >= 64u) {  // a whole wavefront of exact tests
+                        found += soft_drain(g, S, sq_head, 64u, lane);
+                        sq_head = (sq_head + 64u) & (SOFT_Q - 1);
+                        sq_n -= 64u;
+                    }
+                }
             }
             word += (e - t0 < 64u * VT) ? (e - t0 + 63u) / 64u : (uint32_t)VT;
 #pragma unroll
@@ -685,6 +733,9 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 rk[i] = rkn[i];
             }
         }
+    }
+    if constexpr (SOFT) {
+        if (sq_n) found += soft_drain(g, S, sq_head, sq_n, lane);
     }
     wave_lds_sync();
     for (uint32_t k = lane; k < word; k += 64) A.bits[unit * BITW + k] = S.bits[k];
