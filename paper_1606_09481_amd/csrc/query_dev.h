@@ -280,15 +280,27 @@ __device__ __forceinline__ uint32_t edge_test(const Geo &g, const Qv &q, const C
 // transcendental, U in [2^-(j+1), 2^-j) (j from the leading zeros of k)
 // needs f > 2^-(j+1), which needs V < lev[j+1] (with a margin far above the
 // rounding of f); most candidates stop there, so exp and acosh run for few.
-// soft_pre is that first part: true (with U) when the exact test must decide.
-__device__ __forceinline__ bool soft_pre(const Geo &g, double V, uint32_t qi, uint32_t wi, double &U) {
-    if (!(V < g.K)) return false;
+// For j < SOFT_FINE_J the part of [2^-(j+1), 2^-j) that U falls in (the
+// three bits after its leading one) is looked up next: below its acceptance
+// threshold the pair is an edge whatever U is in that part, at or above its
+// rejection threshold it is not; only the pairs in between, about a tenth
+// of those past the level test, take the exact test.
+// soft_pre is that first part: 0 = no edge, 1 = edge, 2 = the exact test
+// must decide (with U).
+__device__ __forceinline__ uint32_t soft_pre(const Geo &g, double V, uint32_t qi, uint32_t wi, double &U) {
+    if (!(V < g.K)) return 0u;
     const uint32_t lo = qi < wi ? qi : wi, hi = qi < wi ? wi : qi;
     const uint64_t k = pair_k(g.pseed, lo, hi);
     const int j = __clzll((long long)k) - 11;  // U in [2^-(j+1), 2^-j); j = -1 for U = 1
-    if (j < 0 || !(V < g.lev[j + 1])) return false;
+    if (j < 0 || !(V < g.lev[j + 1])) return 0u;
     U = (double)k * 0x1p-53;
-    return true;
+    if (j < SOFT_FINE_J) {
+        const int m = (int)((k >> (52 - 3 - j)) & (uint64_t)(SOFT_SUB - 1));
+        const int t = SOFT_SUB * j + (SOFT_SUB - 1 - m);
+        if (!(V < g.stab[t])) return 0u;
+        if (V < g.stab[SOFT_TICKS + t]) return 1u;
+    }
+    return 2u;
 }
 __device__ __forceinline__ uint32_t soft_exact(const Geo &g, double V, double U) {
     const double x = V > 1.0 ? acosh(V) : 0.0;
@@ -678,8 +690,8 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                 // FP64: lanes past the end skip the test (measured faster there)
                 uint32_t r;
                 if (SOFT) {
-                    // no candidate is decided here: those past the level test
-                    // queue for the exact one, which sets their bits later
+                    // the candidates the level and table tests leave open queue
+                    // for the exact test, which sets their bits later
                     r = 0u;
                     double V = 0.0, U = 0.0;
                     bool need = false;
@@ -688,7 +700,9 @@ __device__ __forceinline__ void count_unit(const QueryArgs &A, uint64_t unit, ui
                         const double a = q.hep * c[i].ew.y + q.hem * c[i].ew.x;
                         const double b = (q.sh * (c[i].ew.x - c[i].ew.y)) * (d * d);
                         V = a + b;
-                        need = soft_pre(g, V, S.qi[rk[i]], c[i].wi, U);
+                        const uint32_t pre = soft_pre(g, V, S.qi[rk[i]], c[i].wi, U);
+                        r = pre & 1u;
+                        need = pre == 2u;
                     }
                     const uint64_t nm = __ballot(need);
                     if (need) {

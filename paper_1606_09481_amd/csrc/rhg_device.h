@@ -37,6 +37,10 @@ constexpr int BATCH = 64;        // queries per batch (one wavefront)
 constexpr uint32_t UNIT = RHG_UNIT;  // candidates per work unit (upper bound)
 constexpr uint32_t BITMAP_WORDS = UNIT / 64 + 32;  // decision bitmap words per unit
 constexpr int SOFT_LEVELS = 54;  // probability levels 2^-i, i = 0..53, of the general model
+// Finer levels: U in [2^-(j+1), 2^-j), j < SOFT_FINE_J, cut into SOFT_SUB
+// equal parts by the bits after its leading one (tick t = SOFT_SUB j +
+// SOFT_SUB - 1 - m for part m, so the ticks' lower ends u_t fall with t).
+constexpr int SOFT_SUB = 8, SOFT_FINE_J = 50, SOFT_TICKS = SOFT_SUB * SOFT_FINE_J;
 
 enum SrcMode { SRC_SEED = 0, SRC_COORDS = 1, SRC_TABLE = 2 };
 
@@ -86,6 +90,10 @@ struct Geo {
     double t2;
     uint64_t pseed;
     double lev[SOFT_LEVELS];
+    // stab[t] (t < SOFT_TICKS): a pair at or above it has f < u_t, so no
+    // edge for U >= u_t; stab[SOFT_TICKS + t]: a pair below it has f > the
+    // upper end of tick t's part of U, so an edge (device memory)
+    const double *stab;
 };
 
 __device__ __forceinline__ bool bit_of(const uint32_t *bits, uint32_t s) { return (bits[s >> 5] >> (s & 31u)) & 1u; }

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <stdint.h>
 
 #include <memory>
@@ -18,7 +20,7 @@ enum Slot {
     S_BTAB, S_WIN, S_BCAND, S_BOFF, S_NUNITS, S_UOFF, S_SCANSCR,
     S_UBATCH, S_UEDGES, S_UEOFF, S_STATS, S_SCANSCR2, S_BITS, S_BANDSTART, S_UKEY, S_UORDER, S_UKEY2, S_UORDER2, S_SORTSCR2,
     S_SHARD, S_UDESC, S_MOVED, S_MOVEDO, S_KEEPC, S_KEEPO, S_KEEPERR, S_SCANSCR3,
-    S_CSRROWS, S_CSRROWS2, S_CSRNBRS2, S_CSRSCR, S_CSRERR,
+    S_CSRROWS, S_CSRROWS2, S_CSRNBRS2, S_CSRSCR, S_CSRERR, S_SOFTTAB,
     S_COUNT
 };
 
@@ -39,6 +41,7 @@ struct Ctx {
     void *alloc_user = nullptr;
     SlotBuf slots[S_COUNT];
     hipEvent_t ev[EV_COUNT_] = {};
+    std::vector<double> stab_host;  // the general model's threshold table, as last uploaded
     void *pinned = nullptr;  // 4 KB host readback area
     int exhaustive = 0;
     int ablation = 0;  // RHG_OPT_LITERAL_ABLATION

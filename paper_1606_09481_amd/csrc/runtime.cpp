@@ -364,6 +364,28 @@ void geo_static(const Plan &pl, Geo &g) {
     }
 }
 
+// The general model's finer sure-decision thresholds (Geo::stab), in the
+// levels' terms: f(V) <= u iff acosh V >= x(u) = R + 2T ln(1/u - 1).  The
+// same 2^-30 margin, on the side that makes each shortcut safe: a rejection
+// threshold raised, an acceptance threshold lowered.  Where x(u) is within
+// 1e-6 of 0 neither shortcut is taken (the exact test decides); below it
+// every pair has f < u (always reject); an acceptance needs x(u) > 0.
+static void soft_table(const Plan &pl, std::vector<double> &tab) {
+    tab.assign(2 * SOFT_TICKS, 0.0);
+    auto x_of = [&](double u) { return pl.R + 2.0 * pl.T * std::log(1.0 / u - 1.0); };
+    auto u_of = [](int t) {
+        const int j = t / SOFT_SUB, m = SOFT_SUB - 1 - t % SOFT_SUB;
+        return std::ldexp(1.0 + (double)m / SOFT_SUB, -(j + 1));
+    };
+    for (int t = 0; t < SOFT_TICKS; ++t) {
+        const double xr = x_of(u_of(t));
+        tab[t] = xr < -1e-6 ? -INFINITY : (xr <= 1e-6 ? INFINITY : std::cosh(xr) * (1.0 + 0x1p-30));
+        const double uh = t == 0 ? 1.0 : u_of(t - 1);  // upper end of tick t's part
+        const double xa = uh < 1.0 ? x_of(uh) : -1.0;
+        tab[SOFT_TICKS + t] = xa <= 1e-6 ? -INFINITY : std::cosh(xa) * (1.0 - 0x1p-30);
+    }
+}
+
 int key_bits_for(int B) { return QBITS + std::max(1, ceil_log2((uint64_t)B)); }
 
 constexpr uint64_t UNIT_ORDER_MIN = 8192;
@@ -472,6 +494,12 @@ rhg_status run_count(Ctx *c, const Request &rq, Plan &pl) {
     g.f32 = f32;
     g.btab = btab;
     g.moved = msorted;
+    if (pl.T > 0.0) {  // the general model's finer thresholds (kept on the host until the copy is done)
+        soft_table(pl, c->stab_host);
+        RHG_BUF(stab, double, S_SOFTTAB, 2 * SOFT_TICKS);
+        RHG_HIP(hipMemcpyAsync(stab, c->stab_host.data(), sizeof(double) * 2 * SOFT_TICKS, hipMemcpyHostToDevice, st));
+        g.stab = stab;
+    }
     RHG_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     rhgk::bucket_index(g, btab, st);
 
