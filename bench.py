@@ -422,13 +422,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_traffic_n1e7_a075_k100.md")
 KERNEL_SOURCES = ["query_dev.h", "query.hip", "rhg_device.h", "rhg_kernels.h"]
 
 
-def measured_traffic(key):
+ISSUE_FILE = os.path.join(ROOT, "profiles", "query_issue_n1e7_a075_k100.md")
+# wavefront VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz, a
+# wave64 instruction every 4 cycles on a 16-lane SIMD (the FP64 vector peak,
+# 78.6 TFLOP/s, is 256 x 64 FMA lanes x 2 x 2.4 GHz)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def measured_traffic(key, path=TRAFFIC_FILE, tag="traffic"):
     """HBM bytes per launch of kernel `key` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel sources
-    no longer hash to the ones the counters were taken with."""
+    no longer hash to the ones the counters were taken with.  With
+    path=ISSUE_FILE, tag="valu": its VALU instructions per launch."""
     import hashlib
     try:
-        lines = open(TRAFFIC_FILE).read().split("\n")
+        lines = open(path).read().split("\n")
     except OSError:
         return None, None
     h = hashlib.sha256()
@@ -440,8 +448,8 @@ def measured_traffic(key):
         return None, "counters taken with other kernel sources"
     for l in lines:
         t = l.split()
-        if len(t) == 3 and t[0] == "traffic" and t[1] == key:
-            return int(t[2]), os.path.relpath(TRAFFIC_FILE, ROOT)
+        if len(t) == 3 and t[0] == tag and t[1] == key:
+            return int(t[2]), os.path.relpath(path, ROOT)
     return None, None
 
 
@@ -681,7 +689,21 @@ def main():
     r_emit = roofline("k_emit<false,false>", "k_emit", emit_b, ph["emit"])
     r_count = roofline("k_count<0,false,false>", "k_count", cnt_b, f64["count_kernel_ms"])
     roof, other = (r_emit, r_count) if ph["emit"] >= f64["count_kernel_ms"] else (r_count, r_emit)
-    roof = dict(roof, other=other)
+
+    def issue(kname, kkey, kms):
+        # the same kernel against the chip's VALU issue rate: its wavefront VALU
+        # instructions per launch (committed SQ_INSTS_VALU summary) over its time
+        n_valu, src = measured_traffic(kkey, ISSUE_FILE, "valu") if bench_cfg else (None, None)
+        if n_valu is None:
+            return {"bound": "alu", "kernel": kname, "achieved": None, "source": src}
+        achieved = n_valu / (kms * 1e-3)
+        return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_ISSUE_PEAK,
+                "unit": "wavefront VALU instructions/s", "frac": achieved / VALU_ISSUE_PEAK,
+                "valu_instructions": n_valu, "avg_ms": kms, "source": src}
+
+    roof = dict(roof, other=other, issue=[issue("k_count<0,false,false>", "k_count", f64["count_kernel_ms"]),
+                                          issue("k_emit<false,false>", "k_emit", ph["emit"]),
+                                          issue("k_count<1,false,false>", "k_count_fp32", f32["count_kernel_ms"])])
     line = {
         "metric": METRIC, "value": f64["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * f64["s_per_step"], "higher_is_better": True,
