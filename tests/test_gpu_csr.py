@@ -94,6 +94,22 @@ def test_csr_1e6_degrees_and_rows(ctx):
     assert np.array_equal(ptr, hptr) and np.array_equal(col, hcol)
 
 
+@pytest.mark.parametrize("n,m", [(1, 3), (2, 5), (200, 601), (256, 1000), (257, 999), (65536, 200_001),
+                                 (65537, 200_000), (3_000_000, 1_000_003)])
+def test_csr_any_pair_list(ctx, n, m):
+    """Random pairs (repeats and self-pairs included) for row counts that take
+    1, 2 and 3 sort passes, the first of which reads the pairs themselves: the
+    device CSR equals the host's stable transpose-closure of the same list."""
+    import torch
+    print("case n", n, "m", m, flush=True)
+    rng = np.random.default_rng(n * 7 + m)
+    e = rng.integers(0, n, size=(m, 2), dtype=np.int64).astype(np.int32)
+    dev = torch.from_numpy(e.reshape(-1)).to("cuda")
+    ptr, col = _csr(ctx, n, dev, m)
+    hptr, hcol = _host_rows(e, n)
+    assert np.array_equal(ptr, hptr) and np.array_equal(col, hcol)
+
+
 def test_csr_empty_and_rejects(ctx):
     import torch
     ptr, col = _csr(ctx, 1000, 0, 0)
