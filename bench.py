@@ -645,7 +645,7 @@ def main():
                          "scales HBM byte counters under rocprofv3 --pmc)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[8000.0],
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[6000.0, 8000.0],
                     help="fixed Poisson arrival rates (req/s) at which to also report latency")
     ap.add_argument("--no-configs", action="store_true", help="skip the n = 1e6 and n = 4e6 workloads")
     ap.add_argument("--no-ablation", action="store_true", help="skip the literal-Eq. 3 FP32 ablation")
