@@ -381,8 +381,9 @@ rhg_status rhg_server_submit(rhg_server *s, const rhg_params *params, uint64_t *
 rhg_status rhg_server_wait(rhg_server *s, uint64_t ticket, int timeout_ms, rhg_graph **out, double *latency_ms);
 /* Server counters:
  *   completed    requests finished (success or error)
- *   batched      requests run inside a shared one-launch group of small requests
- *   groups       such launches
+ *   batched      requests run inside a shared group of small requests (one
+ *                host synchronisation per group)
+ *   groups       such groups
  *   fallbacks    grouped requests that outgrew their preallocated scratch or
  *                output slice and were rerun on the multi-launch path
  *   peak_bytes   highest admitted estimated memory in flight

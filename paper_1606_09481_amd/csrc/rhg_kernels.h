@@ -162,12 +162,24 @@ struct SmallDesc {
     unsigned long long *bits;
     uint64_t unit_cap;
     unsigned long long *stats;  // [rechecks, disagreements], zero at launch
+    QueryArgs *qa;              // spread launch only: the request's query arguments (device, written there)
 };
 struct SmallResult {
     uint64_t m, candidates, windows, out_off, rechecks;
+    uint64_t units;  // spread launch: the request's work units (valid with status 0 after its first kernel)
     int status;
 };
 void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
                  unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st);
+// The same group in six launches with no host step in between: one
+// workgroup per request for the tables (a0-a3), the window plan of all the
+// group's batches spread across the chip, one workgroup per request for the
+// batch and unit scans, the count pass over the group's units spread across
+// the chip, one workgroup per request for the edge scan and pool
+// reservation, and the emit pass spread across the chip.  count <=
+// SMALL_GROUP_MAX; every descriptor's qa set.
+constexpr int SMALL_GROUP_MAX = 128;
+void small_group_spread(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
+                        unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st);
 
 }  // namespace rhgk

@@ -4,11 +4,13 @@
 // its own context and HIP stream, take work as soon as they are free and the
 // estimated memory of the work fits the budget next to what is already in
 // flight (a request larger than the whole budget runs alone):
-//   - when the oldest waiting request is small (n <= SMALL_N), it and the
+//   - when the oldest waiting request is small (n <= GROUP_N), it and the
 //     other small requests waiting behind it (up to GROUP_MAX, within the
-//     budget) are generated by one launch of k_small: one workgroup per
-//     request, all phases on the device, one shared output pool, one host
-//     synchronisation for the whole group;
+//     budget) are generated together in six launches with no host step in
+//     between (small_group_spread): the per-request phases by one workgroup
+//     per request, the window plan, count and emit of the whole group over
+//     the chip; one shared output pool, one host synchronisation for the
+//     whole group;
 //   - otherwise the oldest request runs through the multi-launch path
 //     (the rhg_generate path) on the lane's stream.
 // Lanes overlap on the device, so requests that arrive while others run are
@@ -22,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -48,6 +51,11 @@ namespace {
 
 constexpr int N_LANES = 4;
 constexpr int GROUP_MAX = 128;
+// Largest request taken into a group: measured at fixed arrival rates (6000
+// and 8000 requests/s) between 16384 and 98304 points; larger cutoffs raise
+// the saturation rate but put longer setups into the groups.
+constexpr uint64_t GROUP_N = 24576;
+static_assert(GROUP_MAX <= rhgk::SMALL_GROUP_MAX, "a group fits the spread launch");
 
 // ---------------------------------------------------------------------------
 // Device memory cache.  Blocks are handed out by size class and come back on
@@ -216,6 +224,7 @@ struct Lane {
     rhgk::SmallDesc *d_desc = nullptr;
     rhgk::SmallResult *d_res = nullptr;
     unsigned long long *d_zero = nullptr;  // ZERO_WORDS, cleared before every group
+    rhgk::QueryArgs *d_qa = nullptr;       // GROUP_MAX: the requests' query arguments (spread launch)
 };
 
 void finish(SReq *r, rhg_status st, Graph *g) {
@@ -281,14 +290,17 @@ void run_group(Lane &L, std::vector<SReq *> &grp) {
     if (err == RHG_OK && q) {
         for (int k = 0; k < G; ++k)
             if (slot[k] >= 0)
+            {
                 small_fill_desc(L.h_desc[slot[k]], plans[k], grp[k]->rq, lay[k], (char *)L.arena + off[k],
                           L.d_zero + 32 + 2 * slot[k]);
+                L.h_desc[slot[k]].qa = L.d_qa + slot[k];
+            }
         err = hip_status(hipMemsetAsync(L.d_zero, 0, sizeof(unsigned long long) * ZERO_WORDS, st));
         if (err == RHG_OK)
             err = hip_status(hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(rhgk::SmallDesc) * q, hipMemcpyHostToDevice, st));
         if (err == RHG_OK) {
             (void)hipGetLastError();
-            rhgk::small_group(L.d_desc, L.d_res, q, (int2 *)pool->ptr, L.d_zero, pool_pairs, st);
+            rhgk::small_group_spread(L.d_desc, L.d_res, q, (int2 *)pool->ptr, L.d_zero, pool_pairs, st);
             err = hip_status(hipGetLastError());
         }
         if (err == RHG_OK)
@@ -400,6 +412,7 @@ void lane_release(Lane *L, DevCache *C) {
     if (L->d_desc) (void)hipFree(L->d_desc);
     if (L->d_res) (void)hipFree(L->d_res);
     if (L->d_zero) (void)hipFree(L->d_zero);
+    if (L->d_qa) (void)hipFree(L->d_qa);
     rhg_ctx_destroy(reinterpret_cast<rhg_ctx *>(L->ctx));
     if (L->stream) (void)hipStreamDestroy(L->stream);
     delete L;
@@ -448,7 +461,8 @@ extern "C" rhg_status rhg_server_create(int device, uint64_t mem_budget_bytes, r
                 hipSuccess ||
             hipMalloc((void **)&L->d_desc, sizeof(rhgk::SmallDesc) * GROUP_MAX) != hipSuccess ||
             hipMalloc((void **)&L->d_res, sizeof(rhgk::SmallResult) * GROUP_MAX) != hipSuccess ||
-            hipMalloc((void **)&L->d_zero, sizeof(unsigned long long) * ZERO_WORDS) != hipSuccess) {
+            hipMalloc((void **)&L->d_zero, sizeof(unsigned long long) * ZERO_WORDS) != hipSuccess ||
+            hipMalloc((void **)&L->d_qa, sizeof(rhgk::QueryArgs) * GROUP_MAX) != hipSuccess) {
             (void)hipGetLastError();
             st = RHG_ENOMEM;
         }
@@ -502,7 +516,7 @@ extern "C" rhg_status rhg_server_submit(rhg_server *S, const rhg_params *params,
         delete r;
         return st;
     }
-    r->small = r->rq.n <= rhgk::SMALL_N;
+    r->small = r->rq.n <= GROUP_N;
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) {

@@ -1,6 +1,7 @@
-// small.hip -- one-launch generation of many small graphs (serving path).
+// small.hip -- generation of many small graphs together (serving path, and
+// the allocation-free entry point).
 //
-// Each workgroup generates one request of n <= SMALL_N points completely:
+// k_small: each workgroup generates one request completely:
 // sample + slab keys, a workgroup-wide stable LSD radix sort, table gather,
 // slab starts and bucket index, the window plan (plan_batch), batch and unit
 // scans, the count pass (count_unit), the edge scan, an atomic reservation
@@ -9,6 +10,13 @@
 // between them.  The arithmetic (slab keys, windows, distance test, unit
 // walk) is the same code as the multi-launch path, so a request's edge list
 // is byte-identical to rhg_generate's for the same parameters.
+//
+// small_group_spread (the server's groups): the same phases in six launches,
+// the per-request ones (tables; batch and unit scans; edge scan and pool
+// reservation) one workgroup per request, the window plan, count and emit
+// of the whole group one wavefront per batch or unit over the chip.  A
+// group then takes about as long as its largest request's tables, not its
+// whole generation on one CU.
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -146,16 +154,11 @@ __device__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t
     }
 }
 
-__global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, SmallResult *results, int2 *pool,
-                                                      unsigned long long *pool_used, uint64_t pool_cap) {
-    __shared__ QueryArgs sA;
-    __shared__ PhaseSmem P;
-    __shared__ ScanSmem SS;
-    __shared__ uint32_t s_bs[MAX_BANDS + 1];
-    __shared__ int s_flag;
-
-    const SmallDesc &D = descs[blockIdx.x];
-    SmallResult &Z = results[blockIdx.x];
+// Phases a0-a3 of one request by one workgroup (sample, slab keys, sort,
+// slab starts, table, bucket index), leaving its geometry in sA.geo.  False
+// (with Z.status = 1) when the request outgrows its scratch.
+__device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+                             int &s_flag) {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
     __syncthreads();
     if (s_flag) {
         if (t == 0) Z.status = 1;
-        return;
+        return false;
     }
     const Geo &g = sA.geo;
 
@@ -275,10 +278,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
     }
     __syncthreads();
 
-    // ---- a4: window plan per batch, batch scans, units
+    return true;
+}
+
+// Phase a4 after the window plan, by one workgroup: batch and unit scans and
+// the units' batches; the query arguments completed in A (LDS or device
+// memory) and the unit count in U.  False (with Z.status = 1) when the
+// units outgrow the request's scratch.
+__device__ bool small_units(const SmallDesc &D, SmallResult &Z, QueryArgs &A, ScanSmem &SS, uint64_t &U_out) {
+    const int t = threadIdx.x;
+    const uint32_t n = (uint32_t)D.src.n;
     const uint32_t nb = (n + 63) / 64;
-    for (uint32_t b = w; b < nb; b += SM_WAVES) plan_batch(g, D.win, D.bcand, D.bsoff, b, lane);
-    __syncthreads();
     blk_scan_array(D.bcand, D.boff, nb, SS);
     for (uint32_t b = t; b < nb; b += SM_THREADS) D.nunits[b] = (D.bcand[b] + UNIT - 1) / UNIT;
     __syncthreads();
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
     const uint64_t U = D.uoff[nb];
     if (U > D.unit_cap) {
         if (t == 0) Z.status = 1;
-        return;
+        return false;
     }
     for (uint32_t u = t; u < U; u += SM_THREADS) {
         uint32_t lo = 0, hi = nb;
@@ -297,25 +307,51 @@ __global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, Sm
         D.ubatch[u] = lo;
     }
     if (t == 0) {
-        sA.win = D.win;
-        sA.batch_cand = D.bcand;
-        sA.batch_slab_off = D.bsoff;
-        sA.unit_off = D.uoff;
-        sA.unit_batch = D.ubatch;
-        sA.unit_order = nullptr;
-        sA.n_units = U;
-        sA.unit_base = 0;
-        sA.udesc = nullptr;
-        sA.unit_edges = D.uedges;
-        sA.bits = D.bits;
-        sA.unit_edge_off = D.ueoff;
-        sA.out = nullptr;
-        sA.out_capacity = 0;
-        sA.stats = D.stats;
-        sA.exhaustive = 0;
+        A.win = D.win;
+        A.batch_cand = D.bcand;
+        A.batch_slab_off = D.bsoff;
+        A.unit_off = D.uoff;
+        A.unit_batch = D.ubatch;
+        A.unit_order = nullptr;
+        A.n_units = U;
+        A.unit_base = 0;
+        A.udesc = nullptr;
+        A.unit_edges = D.uedges;
+        A.bits = D.bits;
+        A.unit_edge_off = D.ueoff;
+        A.out = nullptr;
+        A.out_capacity = 0;
+        A.stats = D.stats;
+        A.exhaustive = 0;
         Z.candidates = D.boff[nb];
     }
     __syncthreads();
+
+    U_out = U;
+    return true;
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_small(const SmallDesc *descs, SmallResult *results, int2 *pool,
+                                                      unsigned long long *pool_used, uint64_t pool_cap) {
+    __shared__ QueryArgs sA;
+    __shared__ PhaseSmem P;
+    __shared__ ScanSmem SS;
+    __shared__ uint32_t s_bs[MAX_BANDS + 1];
+    __shared__ int s_flag;
+
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint32_t n = (uint32_t)D.src.n;
+    uint64_t U = 0;
+    if (!small_tables(D, Z, sA, P, s_bs, s_flag)) return;
+    // ---- a4: window plan per batch
+    {
+        const uint32_t nb = (n + 63) / 64;
+        for (uint32_t b = w; b < nb; b += SM_WAVES) plan_batch(sA.geo, D.win, D.bcand, D.bsoff, b, lane);
+        __syncthreads();
+    }
+    if (!small_units(D, Z, sA, SS, U)) return;
 
     // ---- a5: count
     for (uint64_t u = w; u < U; u += SM_WAVES) {
@@ -366,6 +402,162 @@ void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *
         hipLaunchKernelGGL(k_small, dim3(count), dim3(SM_THREADS), 0, st, descs, results, pool, pool_used, pool_cap);
 }
 
+// ---- the spread launch: setup per request, then count and emit over the
+// group's units on the whole chip (grid-stride, wavefront per unit)
+
+__global__ __launch_bounds__(SM_THREADS) void k_small_tables(const SmallDesc *descs, SmallResult *results) {
+    __shared__ QueryArgs sA;
+    __shared__ PhaseSmem P;
+    __shared__ uint32_t s_bs[MAX_BANDS + 1];
+    __shared__ int s_flag;
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    if (!small_tables(D, Z, sA, P, s_bs, s_flag)) return;
+    // the query arguments (the geometry so far) to device memory for the next launches, a word per thread
+    static_assert(sizeof(QueryArgs) % 4 == 0, "QueryArgs words");
+    const uint32_t *src = (const uint32_t *)&sA;
+    uint32_t *dst = (uint32_t *)D.qa;
+    for (uint32_t k = threadIdx.x; k < sizeof(QueryArgs) / 4; k += SM_THREADS) dst[k] = src[k];
+    if (threadIdx.x == 0) {
+        Z.units = 0;
+        Z.status = 0;
+    }
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_small_units(const SmallDesc *descs, SmallResult *results) {
+    __shared__ ScanSmem SS;
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    if (Z.status != 0) return;  // uniform: set by the tables launch
+    uint64_t U = 0;
+    if (!small_units(D, Z, *D.qa, SS, U)) return;
+    if (threadIdx.x == 0) Z.units = U;
+}
+
+// Request of global unit k: the last r with pre[r] <= k (pre: prefix of the
+// units of the requests whose setup succeeded, in LDS).
+__device__ __forceinline__ int small_request_of(const uint64_t *pre, int count, uint64_t k) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (pre[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// pre[r] = work items (units, or with BATCHES the 64-query batches) of the
+// requests before r whose status is 0 so far; pre[count] = their total.
+template <bool BATCHES = false>
+__device__ __forceinline__ void small_unit_prefix(const SmallDesc *descs, const SmallResult *results, int count,
+                                                  uint64_t *pre) {
+    if (threadIdx.x == 0) {
+        uint64_t a = 0;
+        for (int r = 0; r < count; ++r) {
+            pre[r] = a;
+            if (results[r].status == 0) a += BATCHES ? (descs[r].src.n + 63) / 64 : results[r].units;
+        }
+        pre[count] = a;
+    }
+    __syncthreads();
+}
+
+constexpr int SP_THREADS = 256, SP_WAVES = SP_THREADS / 64;
+
+// the window plan of every batch of the group, a wavefront per batch
+__global__ __launch_bounds__(SP_THREADS) void k_small_plan(const SmallDesc *descs, const SmallResult *results,
+                                                           int count) {
+    __shared__ uint64_t pre[SMALL_GROUP_MAX + 1];
+    small_unit_prefix<true>(descs, results, count, pre);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t total = pre[count];
+    for (uint64_t k = (uint64_t)blockIdx.x * SP_WAVES + w; k < total; k += (uint64_t)gridDim.x * SP_WAVES) {
+        const int r = small_request_of(pre, count, k);
+        const SmallDesc &D = descs[r];
+        plan_batch(D.qa->geo, D.win, D.bcand, D.bsoff, (uint32_t)(k - pre[r]), lane);
+    }
+}
+
+__global__ __launch_bounds__(SP_THREADS) void k_small_count(const SmallDesc *descs, const SmallResult *results,
+                                                            int count) {
+    // one LDS area per wavefront, for either precision: the wavefronts of
+    // a workgroup take units of different requests
+    union WaveCount {
+        CountSmem<0> c0;
+        CountSmem<1> c1;
+    };
+    __shared__ uint64_t pre[SMALL_GROUP_MAX + 1];
+    __shared__ WaveCount S[SP_WAVES];
+    small_unit_prefix(descs, results, count, pre);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t total = pre[count];
+    for (uint64_t k = (uint64_t)blockIdx.x * SP_WAVES + w; k < total; k += (uint64_t)gridDim.x * SP_WAVES) {
+        const int r = small_request_of(pre, count, k);
+        const uint64_t u = k - pre[r];
+        const QueryArgs &A = *descs[r].qa;
+        if (descs[r].fp32) count_unit<1, false>(A, u, u, lane, S[w].c1);
+        else count_unit<0, false>(A, u, u, lane, S[w].c0);
+    }
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_small_scan(const SmallDesc *descs, SmallResult *results, int2 *pool,
+                                                           unsigned long long *pool_used, uint64_t pool_cap) {
+    __shared__ ScanSmem SS;
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    if (Z.status != 0) return;  // uniform: set by the setup launch
+    const uint32_t U = (uint32_t)Z.units;
+    blk_scan_array(D.uedges, D.ueoff, U, SS);
+    if (threadIdx.x == 0) {
+        // the pool reservation of the one-launch path
+        const uint64_t m = D.ueoff[U];
+        unsigned long long cur = atomicAdd(pool_used, 0ull), off = 0;
+        int fits = 0;
+        for (;;) {
+            if (cur + m > pool_cap) break;
+            const unsigned long long prev = atomicCAS(pool_used, cur, cur + m);
+            if (prev == cur) {
+                off = cur;
+                fits = 1;
+                break;
+            }
+            cur = prev;
+        }
+        Z.m = m;
+        Z.out_off = off;
+        Z.rechecks = atomicAdd(&D.stats[0], 0ull);
+        D.qa->out = pool + off;
+        D.qa->out_capacity = m;
+        if (!fits) Z.status = 2;
+    }
+}
+
+__global__ __launch_bounds__(SP_THREADS) void k_small_emit(const SmallDesc *descs, const SmallResult *results,
+                                                           int count) {
+    __shared__ uint64_t pre[SMALL_GROUP_MAX + 1];
+    __shared__ EmitSmem S[SP_WAVES];
+    small_unit_prefix(descs, results, count, pre);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t total = pre[count];
+    for (uint64_t k = (uint64_t)blockIdx.x * SP_WAVES + w; k < total; k += (uint64_t)gridDim.x * SP_WAVES) {
+        const int r = small_request_of(pre, count, k);
+        const uint64_t u = k - pre[r];
+        // decision words from the count launch: scalar loads
+        emit_unit<false, true>(*descs[r].qa, u, u, lane, S[w]);
+    }
+}
+
+void small_group_spread(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
+                        unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st) {
+    if (count <= 0 || count > SMALL_GROUP_MAX) return;
+    const unsigned spread = 1024;  // workgroups of 4 wavefronts: 4 per CU
+    hipLaunchKernelGGL(k_small_tables, dim3(count), dim3(SM_THREADS), 0, st, descs, results);
+    hipLaunchKernelGGL(k_small_plan, dim3(spread), dim3(SP_THREADS), 0, st, descs, results, count);
+    hipLaunchKernelGGL(k_small_units, dim3(count), dim3(SM_THREADS), 0, st, descs, results);
+    hipLaunchKernelGGL(k_small_count, dim3(spread), dim3(SP_THREADS), 0, st, descs, results, count);
+    hipLaunchKernelGGL(k_small_scan, dim3(count), dim3(SM_THREADS), 0, st, descs, results, pool, pool_used, pool_cap);
+    hipLaunchKernelGGL(k_small_emit, dim3(spread), dim3(SP_THREADS), 0, st, descs, results, count);
+}
+
 }  // namespace rhgk
 
 // ---------------------------------------------------------------------------
@@ -389,7 +581,9 @@ SmallLayout small_layout_units(uint64_t n, int B, uint64_t unit_cap, bool fp32) 
     if (fp32) b += align256(8 * n);                    // f32
     b += align256(4 * L.btab_cap) + align256(8 * L.win_cap);
     b += 2 * align256(8 * nb) + 2 * align256(8 * (nb + 1)) + align256(8 * nb * (uint64_t)(B + 1));
-    b += 2 * align256(4 * L.unit_cap) + align256(8 * (L.unit_cap + 1)) + align256(8 * L.unit_cap * BITMAP_WORDS);
+    // (the bitmap with 64 bytes past its last unit: the spread emit reads a
+    // step's words as one run, up to 4 words past a unit's last)
+    b += 2 * align256(4 * L.unit_cap) + align256(8 * (L.unit_cap + 1)) + align256(8 * L.unit_cap * BITMAP_WORDS + 64);
     L.bytes = b;
     return L;
 }
@@ -434,7 +628,7 @@ void small_fill_desc(rhgk::SmallDesc &D, const Plan &pl, const Request &rq, cons
     D.ubatch = (uint32_t *)take(4 * D.unit_cap);
     D.uedges = (uint32_t *)take(4 * D.unit_cap);
     D.ueoff = (uint64_t *)take(8 * (D.unit_cap + 1));
-    D.bits = (unsigned long long *)take(8 * D.unit_cap * BITMAP_WORDS);
+    D.bits = (unsigned long long *)take(8 * D.unit_cap * BITMAP_WORDS + 64);
     D.stats = stats;
 }
 
