@@ -423,10 +423,11 @@ KERNEL_SOURCES = ["query_dev.h", "query.hip", "rhg_device.h", "rhg_kernels.h"]
 
 
 ISSUE_FILE = os.path.join(ROOT, "profiles", "query_issue_n1e7_a075_k100.md")
-# wavefront VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz, a
-# wave64 instruction every 4 cycles on a 16-lane SIMD (the FP64 vector peak,
-# 78.6 TFLOP/s, is 256 x 64 FMA lanes x 2 x 2.4 GHz)
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# SIMD cycles per second: 256 CUs x 4 SIMDs x 2.4 GHz.  A wavefront VALU
+# instruction takes 2 of them for 32-bit operations (the FP32 vector peak,
+# 157.3 TFLOP/s = 256 x 128 FMA lanes x 2 x 2.4 GHz) and 4 for FP64
+# arithmetic (78.6 TFLOP/s).
+VALU_CYCLE_PEAK = 256 * 4 * 2.4e9
 
 
 def measured_traffic(key, path=TRAFFIC_FILE, tag="traffic"):
@@ -691,15 +692,19 @@ def main():
     roof, other = (r_emit, r_count) if ph["emit"] >= f64["count_kernel_ms"] else (r_count, r_emit)
 
     def issue(kname, kkey, kms):
-        # the same kernel against the chip's VALU issue rate: its wavefront VALU
-        # instructions per launch (committed SQ_INSTS_VALU summary) over its time
+        # the same kernel against the chip's VALU cycles: its wavefront VALU
+        # instructions per launch (committed SQ_INSTS_VALU and FP64 counts) at
+        # 2 SIMD cycles each, 4 for FP64 arithmetic, over its time
         n_valu, src = measured_traffic(kkey, ISSUE_FILE, "valu") if bench_cfg else (None, None)
-        if n_valu is None:
+        n_f64, _ = measured_traffic(kkey, ISSUE_FILE, "valu_f64") if bench_cfg else (None, None)
+        if n_valu is None or n_f64 is None:
             return {"bound": "alu", "kernel": kname, "achieved": None, "source": src}
-        achieved = n_valu / (kms * 1e-3)
-        return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_ISSUE_PEAK,
-                "unit": "wavefront VALU instructions/s", "frac": achieved / VALU_ISSUE_PEAK,
-                "valu_instructions": n_valu, "avg_ms": kms, "source": src}
+        cycles = 2 * (n_valu - n_f64) + 4 * n_f64
+        achieved = cycles / (kms * 1e-3)
+        return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_CYCLE_PEAK,
+                "unit": "SIMD VALU cycles/s", "frac": achieved / VALU_CYCLE_PEAK,
+                "valu_instructions": n_valu, "valu_f64_instructions": n_f64, "valu_cycles": cycles,
+                "avg_ms": kms, "source": src}
 
     roof = dict(roof, other=other, issue=[issue("k_count<0,false,false>", "k_count", f64["count_kernel_ms"]),
                                           issue("k_emit<false,false>", "k_emit", ph["emit"]),
