@@ -36,7 +36,7 @@ def _edges(g):
     return e, st
 
 
-def _mix(seed, count, n_lo=300, n_hi=16384, large=()):
+def _mix(seed, count, n_lo=300, n_hi=24576, large=()):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
