@@ -447,16 +447,25 @@ __device__ __forceinline__ int small_request_of(const uint64_t *pre, int count, 
 
 // pre[r] = work items (units, or with BATCHES the 64-query batches) of the
 // requests before r whose status is 0 so far; pre[count] = their total.
+// (count <= 128: the first wavefront scans two entries per lane)
 template <bool BATCHES = false>
 __device__ __forceinline__ void small_unit_prefix(const SmallDesc *descs, const SmallResult *results, int count,
                                                   uint64_t *pre) {
-    if (threadIdx.x == 0) {
-        uint64_t a = 0;
-        for (int r = 0; r < count; ++r) {
-            pre[r] = a;
-            if (results[r].status == 0) a += BATCHES ? (descs[r].src.n + 63) / 64 : results[r].units;
-        }
-        pre[count] = a;
+    static_assert(SMALL_GROUP_MAX <= 128, "two entries per lane");
+    if (threadIdx.x < 64) {
+        const int l = (int)threadIdx.x;
+        auto items = [&](int r) -> uint64_t {
+            if (r >= count || results[r].status != 0) return 0;
+            return BATCHES ? (descs[r].src.n + 63) / 64 : results[r].units;
+        };
+        const uint64_t v0 = items(l), v1 = items(l + 64);
+        const uint64_t i0 = wave_incl_scan_u64(v0);
+        const uint64_t t0 = __shfl(i0, 63, 64);
+        const uint64_t i1 = t0 + wave_incl_scan_u64(v1);
+        if (l < count) pre[l] = i0 - v0;
+        if (l + 64 < count) pre[l + 64] = i1 - v1;
+        const uint64_t total = __shfl(i1, 63, 64);
+        if (l == 0) pre[count] = total;
     }
     __syncthreads();
 }
