@@ -143,7 +143,6 @@ void query_emit(const QueryArgs &a, int fp32, hipStream_t st);
 // capacities (stats zeroed); the device writes one SmallResult per request.
 // status: 0 done, 1 scratch too small (rerun on the multi-launch path),
 // 2 output pool full (same).
-constexpr uint32_t SMALL_N = 16384;
 struct SmallDesc {
     rhgd::Source src;
     rhgd::Geo geo;
