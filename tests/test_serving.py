@@ -157,6 +157,27 @@ def test_request_larger_than_budget_runs_alone(ctx):
     assert np.array_equal(e2, _edges(rhg.rhg_generate(ctx, p_small))[0])
 
 
+def test_group_edges_of_sizes(ctx):
+    """Requests at the sizes where batches and the group cutoff change (a few
+    points, one batch and a point more, 24576 and 24577 points: the last
+    grouped size and the first one that is not), submitted together: each
+    equals rhg_generate alone."""
+    reqs = [rhg.params(n, 1.0, R=4.0 + 0.5 * k, seed=100 + n) for k, n in enumerate((2, 3, 63, 64, 65, 127, 129))]
+    reqs += [rhg.params(n, 0.9, kbar=12.0, seed=7 + n) for n in (24576, 24577)]
+    srv = rhg.rhg_server_create(0, 4 << 30)
+    try:
+        tickets = [rhg.rhg_server_submit(srv, p) for p in reqs]
+        served = [_edges(rhg.rhg_server_wait(srv, t)[0]) for t in tickets]
+        cnt = rhg.rhg_server_counters(srv)
+    finally:
+        rhg.rhg_server_destroy(srv)
+    print("counters", cnt, flush=True)
+    assert cnt["completed"] == len(reqs) and cnt["batched"] >= len(reqs) - 1
+    for p, (e, _) in zip(reqs, served):
+        ref, _ = _edges(rhg.rhg_generate(ctx, p))
+        assert e.shape == ref.shape and np.array_equal(e, ref), _describe(p)
+
+
 def test_ticket_semantics():
     srv = rhg.rhg_server_create(0, 1 << 30)
     try:
