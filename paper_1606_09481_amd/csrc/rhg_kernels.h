@@ -170,13 +170,15 @@ struct SmallResult {
 };
 void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
                  unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st);
-// The same group in six launches with no host step in between: one
-// workgroup per request for the tables (a0-a3), the window plan of all the
-// group's batches spread across the chip, one workgroup per request for the
-// batch and unit scans, the count pass over the group's units spread across
-// the chip, one workgroup per request for the edge scan and pool
-// reservation, and the emit pass spread across the chip.  count <=
-// SMALL_GROUP_MAX; every descriptor's qa set.
+// The same group in seven launches with no host step in between: the keys
+// of all the group's points spread across the chip (a0, a2), one workgroup
+// per request for the sort, slab starts and bucket index (a3), the table
+// rows and window plan of all the group's batches spread across the chip
+// (a1, a4), one workgroup per request for the batch and unit scans, the
+// count pass over the group's units spread across the chip, one workgroup
+// per request for the edge scan and pool reservation, and the emit pass
+// spread across the chip.  count <= SMALL_GROUP_MAX; every descriptor's qa
+// set.
 constexpr int SMALL_GROUP_MAX = 128;
 void small_group_spread(const SmallDesc *descs, SmallResult *results, int count, int2 *pool,
                         unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st);

@@ -6,11 +6,11 @@
 // flight (a request larger than the whole budget runs alone):
 //   - when the oldest waiting request is small (n <= GROUP_N), it and the
 //     other small requests waiting behind it (up to GROUP_MAX, within the
-//     budget) are generated together in six launches with no host step in
-//     between (small_group_spread): the per-request phases by one workgroup
-//     per request, the window plan, count and emit of the whole group over
-//     the chip; one shared output pool, one host synchronisation for the
-//     whole group;
+//     budget) are generated together in seven launches with no host step
+//     in between (small_group_spread): the sort and the scans by one
+//     workgroup per request, the keys, table rows and window plan, count and
+//     emit of the whole group over the chip; one shared output pool, one
+//     host synchronisation for the whole group;
 //   - otherwise the oldest request runs through the multi-launch path
 //     (the rhg_generate path) on the lane's stream.
 // Lanes overlap on the device, so requests that arrive while others run are

@@ -11,11 +11,12 @@
 // walk) is the same code as the multi-launch path, so a request's edge list
 // is byte-identical to rhg_generate's for the same parameters.
 //
-// small_group_spread (the server's groups): the same phases in six launches,
-// the per-request ones (tables; batch and unit scans; edge scan and pool
-// reservation) one workgroup per request, the window plan, count and emit
-// of the whole group one wavefront per batch or unit over the chip.  A
-// group then takes about as long as its largest request's tables, not its
+// small_group_spread (the server's groups): the same phases in seven
+// launches, the per-request ones (sort, slab starts and bucket index; batch
+// and unit scans; edge scan and pool reservation) one workgroup per request,
+// the keys, the table rows with the window plan, the count and the emit of
+// the whole group one wavefront per 64 points or per unit over the chip.  A
+// group then takes about as long as its largest request's sort, not its
 // whole generation on one CU.
 #include <cmath>
 #include <cstring>
@@ -154,32 +155,38 @@ __device__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t
     }
 }
 
-// Phases a0-a3 of one request by one workgroup (sample, slab keys, sort,
-// slab starts, table, bucket index), leaving its geometry in sA.geo.  False
-// (with Z.status = 1) when the request outgrows its scratch.
-__device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
-                             int &s_flag) {
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+// a0 + a2 of point i: its sample, slab (thresholds of the static geometry
+// g) and key, with the payload i.
+__device__ __forceinline__ void small_key_of(const SmallDesc &D, const Geo &g, uint32_t i) {
+    double th, r;
+    load_point(D.src, i, th, r);
+    int b = 0;
+    while (b + 1 < g.B && g.c[b + 1] <= r) ++b;
+    D.keys[i] = ((uint32_t)b << QBITS) | qang(th);
+    D.vals[i] = i;
+}
+
+// a1 of sorted position s: the table row of the point there.
+__device__ __forceinline__ void small_row_of(const SmallDesc &D, uint32_t s) {
+    const uint32_t v = D.vals[s];
+    double th, r, a, b, c, d, e;
+    load_point(D.src, v, th, r);
+    point_table(D.src, v, th, r, a, b, c, d, e);
+    D.th[s] = th;
+    D.epm[s] = make_double2(a, b);
+    D.hsc[s] = make_double2(d, e);
+    if (D.f32) D.f32[s] = make_float2((float)a, (float)b);
+}
+
+// a3 and the layout, by one workgroup, after the keys: stable LSD radix sort
+// (result back in keys/vals), slab starts, bucket bits and window bases in
+// sA.geo (whose static part is set).  False (with Z.status = 1) when the
+// request outgrows its scratch.
+__device__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+                                  int &s_flag) {
+    const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
-    if (t == 0) {
-        sA.geo = D.geo;  // static part: n, B, R, K, Kw, FP32 thresholds, c, sinh/exp/reciprocal constants
-        s_flag = 0;
-    }
-    __syncthreads();
-
-    // ---- a0 + a2: sample, slab, key
-    for (uint32_t i = t; i < n; i += SM_THREADS) {
-        double th, r;
-        load_point(D.src, i, th, r);
-        int b = 0;
-        while (b + 1 < B && sA.geo.c[b + 1] <= r) ++b;
-        D.keys[i] = ((uint32_t)b << QBITS) | qang(th);
-        D.vals[i] = i;
-    }
-    __syncthreads();
-
-    // ---- a3: stable LSD radix sort (result back in keys/vals after an even number of passes)
     {
         const int passes = (D.key_bits + 7) / 8;
         uint32_t *ka = D.keys, *va = D.vals, *kb = D.keys2, *vb = D.vals2;
@@ -197,7 +204,6 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
     }
     __syncthreads();
 
-    // ---- slab starts, then layout (bucket bits, window bases) in the LDS copy of the geometry
     if (t <= B) {
         uint32_t lo = 0, hi = n;
         if (t == B) {
@@ -243,22 +249,13 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
         if (t == 0) Z.status = 1;
         return false;
     }
-    const Geo &g = sA.geo;
+    return true;
+}
 
-    // ---- a1: table in sorted order
-    for (uint32_t s = t; s < n; s += SM_THREADS) {
-        const uint32_t v = D.vals[s];
-        double th, r, a, b, c, d, e;
-        load_point(D.src, v, th, r);
-        point_table(D.src, v, th, r, a, b, c, d, e);
-        D.th[s] = th;
-        D.epm[s] = make_double2(a, b);
-        D.hsc[s] = make_double2(d, e);
-        if (D.f32) D.f32[s] = make_float2((float)a, (float)b);
-    }
-    __syncthreads();
-
-    // ---- slab bucket index
+// The slab bucket index of the sorted keys, by one workgroup.
+__device__ void small_bucket(const SmallDesc &D, const Geo &g) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint32_t n = (uint32_t)D.src.n;
     for (uint32_t s = t; s < n; s += SM_THREADS) {
         const uint32_t key = D.keys[s];
         const int j = (int)(key >> QBITS);
@@ -268,7 +265,7 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
         uint32_t *T = D.btab + g.bto[j];
         for (int64_t k = bp + 1; k <= b; ++k) T[k] = s;
     }
-    for (int j = w; j < B; j += SM_WAVES) {
+    for (int j = w; j < g.B; j += SM_WAVES) {
         const uint32_t nbk = 1u << (QBITS - g.bshift[j]);
         uint32_t *T = D.btab + g.bto[j];
         const uint32_t bs = g.bs[j], be = g.bs[j + 1];
@@ -276,8 +273,26 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
         if (be > bs) first = (int64_t)((D.keys[be - 1] & QMASK) >> g.bshift[j]) + 1;
         for (int64_t k = first + lane; k <= (int64_t)nbk; k += 64) T[k] = be;
     }
-    __syncthreads();
+}
 
+// Phases a0-a3 of one request by one workgroup (sample, slab keys, sort,
+// slab starts, table, bucket index), leaving its geometry in sA.geo.  False
+// (with Z.status = 1) when the request outgrows its scratch.
+__device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+                             int &s_flag) {
+    const int t = threadIdx.x;
+    const uint32_t n = (uint32_t)D.src.n;
+    if (t == 0) {
+        sA.geo = D.geo;  // static part: n, B, R, K, Kw, FP32 thresholds, c, sinh/exp/reciprocal constants
+        s_flag = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += SM_THREADS) small_key_of(D, sA.geo, i);
+    __syncthreads();
+    if (!small_sort_layout(D, Z, sA, P, s_bs, s_flag)) return false;
+    for (uint32_t s = t; s < n; s += SM_THREADS) small_row_of(D, s);
+    small_bucket(D, sA.geo);
+    __syncthreads();
     return true;
 }
 
@@ -402,40 +417,12 @@ void small_group(const SmallDesc *descs, SmallResult *results, int count, int2 *
         hipLaunchKernelGGL(k_small, dim3(count), dim3(SM_THREADS), 0, st, descs, results, pool, pool_used, pool_cap);
 }
 
-// ---- the spread launch: setup per request, then count and emit over the
-// group's units on the whole chip (grid-stride, wavefront per unit)
+// ---- the spread launch: the per-point work (keys; table rows with the
+// window plan) and the count and emit over the whole chip (grid-stride,
+// wavefront per 64 points or per unit), the sort and scans per request
 
-__global__ __launch_bounds__(SM_THREADS) void k_small_tables(const SmallDesc *descs, SmallResult *results) {
-    __shared__ QueryArgs sA;
-    __shared__ PhaseSmem P;
-    __shared__ uint32_t s_bs[MAX_BANDS + 1];
-    __shared__ int s_flag;
-    const SmallDesc &D = descs[blockIdx.x];
-    SmallResult &Z = results[blockIdx.x];
-    if (!small_tables(D, Z, sA, P, s_bs, s_flag)) return;
-    // the query arguments (the geometry so far) to device memory for the next launches, a word per thread
-    static_assert(sizeof(QueryArgs) % 4 == 0, "QueryArgs words");
-    const uint32_t *src = (const uint32_t *)&sA;
-    uint32_t *dst = (uint32_t *)D.qa;
-    for (uint32_t k = threadIdx.x; k < sizeof(QueryArgs) / 4; k += SM_THREADS) dst[k] = src[k];
-    if (threadIdx.x == 0) {
-        Z.units = 0;
-        Z.status = 0;
-    }
-}
-
-__global__ __launch_bounds__(SM_THREADS) void k_small_units(const SmallDesc *descs, SmallResult *results) {
-    __shared__ ScanSmem SS;
-    const SmallDesc &D = descs[blockIdx.x];
-    SmallResult &Z = results[blockIdx.x];
-    if (Z.status != 0) return;  // uniform: set by the tables launch
-    uint64_t U = 0;
-    if (!small_units(D, Z, *D.qa, SS, U)) return;
-    if (threadIdx.x == 0) Z.units = U;
-}
-
-// Request of global unit k: the last r with pre[r] <= k (pre: prefix of the
-// units of the requests whose setup succeeded, in LDS).
+// Request of global item k: the last r with pre[r] <= k (pre: prefix of the
+// items of the requests taking part, in LDS).
 __device__ __forceinline__ int small_request_of(const uint64_t *pre, int count, uint64_t k) {
     int lo = 0, hi = count;
     while (hi - lo > 1) {
@@ -445,18 +432,22 @@ __device__ __forceinline__ int small_request_of(const uint64_t *pre, int count, 
     return lo;
 }
 
-// pre[r] = work items (units, or with BATCHES the 64-query batches) of the
-// requests before r whose status is 0 so far; pre[count] = their total.
+// pre[r] = work items of the requests before r, pre[count] = their total.
+// Items: units, or 64-point batches, of the requests whose status is 0 so
+// far; or (ITEM_BATCHES_ALL, the group's first launch, before any status is
+// written) the 64-point batches of every request.
 // (count <= 128: the first wavefront scans two entries per lane)
-template <bool BATCHES = false>
+constexpr int ITEM_UNITS = 0, ITEM_BATCHES = 1, ITEM_BATCHES_ALL = 2;
+template <int ITEMS = ITEM_UNITS>
 __device__ __forceinline__ void small_unit_prefix(const SmallDesc *descs, const SmallResult *results, int count,
                                                   uint64_t *pre) {
     static_assert(SMALL_GROUP_MAX <= 128, "two entries per lane");
     if (threadIdx.x < 64) {
         const int l = (int)threadIdx.x;
         auto items = [&](int r) -> uint64_t {
-            if (r >= count || results[r].status != 0) return 0;
-            return BATCHES ? (descs[r].src.n + 63) / 64 : results[r].units;
+            if (r >= count) return 0;
+            if (ITEMS != ITEM_BATCHES_ALL && results[r].status != 0) return 0;
+            return ITEMS == ITEM_UNITS ? results[r].units : (descs[r].src.n + 63) / 64;
         };
         const uint64_t v0 = items(l), v1 = items(l + 64);
         const uint64_t i0 = wave_incl_scan_u64(v0);
@@ -472,18 +463,74 @@ __device__ __forceinline__ void small_unit_prefix(const SmallDesc *descs, const 
 
 constexpr int SP_THREADS = 256, SP_WAVES = SP_THREADS / 64;
 
-// the window plan of every batch of the group, a wavefront per batch
-__global__ __launch_bounds__(SP_THREADS) void k_small_plan(const SmallDesc *descs, const SmallResult *results,
-                                                           int count) {
+// a0 + a2 of every point of the group: sample, slab and key, a wavefront per 64 points
+__global__ __launch_bounds__(SP_THREADS) void k_small_keys(const SmallDesc *descs, int count) {
     __shared__ uint64_t pre[SMALL_GROUP_MAX + 1];
-    small_unit_prefix<true>(descs, results, count, pre);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    small_unit_prefix<ITEM_BATCHES_ALL>(descs, nullptr, count, pre);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const uint64_t total = pre[count];
     for (uint64_t k = (uint64_t)blockIdx.x * SP_WAVES + w; k < total; k += (uint64_t)gridDim.x * SP_WAVES) {
         const int r = small_request_of(pre, count, k);
         const SmallDesc &D = descs[r];
-        plan_batch(D.qa->geo, D.win, D.bcand, D.bsoff, (uint32_t)(k - pre[r]), lane);
+        const uint32_t i = (uint32_t)(k - pre[r]) * 64u + (uint32_t)lane;
+        if (i < (uint32_t)D.src.n) small_key_of(D, D.geo, i);
     }
+}
+
+// a3 per request, one workgroup each: sort, slab starts, layout and bucket
+// index; the query arguments (the geometry so far) then go to device memory
+// for the next launches, and the status is set
+__global__ __launch_bounds__(SM_THREADS) void k_small_sort(const SmallDesc *descs, SmallResult *results) {
+    __shared__ QueryArgs sA;
+    __shared__ PhaseSmem P;
+    __shared__ uint32_t s_bs[MAX_BANDS + 1];
+    __shared__ int s_flag;
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    if (threadIdx.x == 0) {
+        sA.geo = D.geo;  // static part, as in small_tables
+        s_flag = 0;
+    }
+    __syncthreads();
+    if (!small_sort_layout(D, Z, sA, P, s_bs, s_flag)) return;
+    small_bucket(D, sA.geo);
+    static_assert(sizeof(QueryArgs) % 4 == 0, "QueryArgs words");
+    const uint32_t *src = (const uint32_t *)&sA;
+    uint32_t *dst = (uint32_t *)D.qa;
+    for (uint32_t k = threadIdx.x; k < sizeof(QueryArgs) / 4; k += SM_THREADS) dst[k] = src[k];
+    if (threadIdx.x == 0) {
+        Z.units = 0;
+        Z.status = 0;
+    }
+}
+
+// a1 and a4 of every batch of the group, a wavefront per batch: the table
+// rows of its 64 points, then their windows (the plan reads back only the
+// rows this lane has just written)
+__global__ __launch_bounds__(SP_THREADS) void k_small_plan(const SmallDesc *descs, const SmallResult *results,
+                                                           int count) {
+    __shared__ uint64_t pre[SMALL_GROUP_MAX + 1];
+    small_unit_prefix<ITEM_BATCHES>(descs, results, count, pre);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const uint64_t total = pre[count];
+    for (uint64_t k = (uint64_t)blockIdx.x * SP_WAVES + w; k < total; k += (uint64_t)gridDim.x * SP_WAVES) {
+        const int r = small_request_of(pre, count, k);
+        const SmallDesc &D = descs[r];
+        const uint32_t b = (uint32_t)(k - pre[r]);
+        const uint32_t s = b * 64u + (uint32_t)lane;
+        if (s < (uint32_t)D.src.n) small_row_of(D, s);
+        plan_batch(D.qa->geo, D.win, D.bcand, D.bsoff, b, lane);
+    }
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_small_units(const SmallDesc *descs, SmallResult *results) {
+    __shared__ ScanSmem SS;
+    const SmallDesc &D = descs[blockIdx.x];
+    SmallResult &Z = results[blockIdx.x];
+    if (Z.status != 0) return;  // uniform: set by the sort launch
+    uint64_t U = 0;
+    if (!small_units(D, Z, *D.qa, SS, U)) return;
+    if (threadIdx.x == 0) Z.units = U;
 }
 
 __global__ __launch_bounds__(SP_THREADS) void k_small_count(const SmallDesc *descs, const SmallResult *results,
@@ -559,7 +606,8 @@ void small_group_spread(const SmallDesc *descs, SmallResult *results, int count,
                         unsigned long long *pool_used, uint64_t pool_cap, hipStream_t st) {
     if (count <= 0 || count > SMALL_GROUP_MAX) return;
     const unsigned spread = 1024;  // workgroups of 4 wavefronts: 4 per CU
-    hipLaunchKernelGGL(k_small_tables, dim3(count), dim3(SM_THREADS), 0, st, descs, results);
+    hipLaunchKernelGGL(k_small_keys, dim3(spread), dim3(SP_THREADS), 0, st, descs, count);
+    hipLaunchKernelGGL(k_small_sort, dim3(count), dim3(SM_THREADS), 0, st, descs, results);
     hipLaunchKernelGGL(k_small_plan, dim3(spread), dim3(SP_THREADS), 0, st, descs, results, count);
     hipLaunchKernelGGL(k_small_units, dim3(count), dim3(SM_THREADS), 0, st, descs, results);
     hipLaunchKernelGGL(k_small_count, dim3(spread), dim3(SP_THREADS), 0, st, descs, results, count);
