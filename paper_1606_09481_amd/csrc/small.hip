@@ -33,10 +33,12 @@ constexpr int SM_WAVES = SM_THREADS / 64;
 constexpr int SM_ITEMS = 16;
 constexpr int SM_TILE = SM_THREADS * SM_ITEMS;  // keys ranked per sort step
 
+constexpr int SM_MAX_PASSES = 4;
 struct SortSmem {
     uint32_t h[256];
     uint32_t off[256];
     uint32_t wcnt[SM_WAVES][256];
+    uint32_t dig[SM_MAX_PASSES][256];  // digit counts of every pass
 };
 struct ScanSmem {
     uint64_t wsum[SM_WAVES];
@@ -65,7 +67,7 @@ __device__ __forceinline__ uint64_t blk_excl_scan(uint64_t x, uint64_t *total, S
 
 // out[0..len] = exclusive prefix of in[0..len) (out[len] = total), one workgroup.
 template <typename T>
-__device__ void blk_scan_array(const T *in, uint64_t *out, uint32_t len, ScanSmem &S) {
+__device__ __forceinline__ void blk_scan_array(const T *in, uint64_t *out, uint32_t len, ScanSmem &S) {
     uint64_t carry = 0;
     for (uint32_t base = 0; base < len; base += SM_THREADS) {
         const uint32_t i = base + threadIdx.x;
@@ -79,18 +81,41 @@ __device__ void blk_scan_array(const T *in, uint64_t *out, uint32_t len, ScanSme
     __syncthreads();
 }
 
-// One stable LSD pass (8-bit digit at `shift`) of n keys with payload.
-__device__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n,
-                              int shift, SortSmem &S) {
+// The digit counts of every pass into S.dig, from one read of the keys
+// (they do not depend on the order), SM_UNROLL keys per thread in flight.
+constexpr int SM_UNROLL = 8;
+__device__ __forceinline__ void blk_digit_counts(const uint32_t *keys, uint32_t n, int passes, SortSmem &S) {
+    const int t = threadIdx.x;
+    for (int x = t; x < SM_MAX_PASSES * 256; x += SM_THREADS) S.dig[x >> 8][x & 255] = 0;
+    __syncthreads();
+    for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
+        uint32_t k[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {  // unconditional loads (index clamped): all in flight at once
+            const uint32_t i = base + (uint32_t)u * SM_THREADS;
+            k[u] = keys[i < n ? i : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            if (base + (uint32_t)u * SM_THREADS < n) {
+#pragma unroll
+                for (int p = 0; p < SM_MAX_PASSES; ++p)
+                    if (p < passes) atomicAdd(&S.dig[p][(k[u] >> (8 * p)) & 255u], 1u);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// One stable LSD pass (8-bit digit at `shift`) of n keys with payload;
+// cnt: the digit counts of this pass (S.dig).
+__device__ __forceinline__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n,
+                              int shift, const uint32_t *cnt, SortSmem &S) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    if (t < 256) S.h[t] = 0;
-    __syncthreads();
-    for (uint32_t i = t; i < n; i += SM_THREADS) atomicAdd(&S.h[(kin[i] >> shift) & 255u], 1u);
-    __syncthreads();
     if (t < 64) {  // exclusive scan of 256 counts by one wavefront, 4 per lane
         uint32_t c[4], s = 0;
         for (int k = 0; k < 4; ++k) {
-            c[k] = S.h[4 * t + k];
+            c[k] = cnt[4 * t + k];
             s += c[k];
         }
         const uint32_t ex = wave_incl_scan_u32(s) - s;
@@ -108,11 +133,15 @@ __device__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t
         const uint32_t wb = base + (uint32_t)w * (SM_ITEMS * 64);
         uint32_t k[SM_ITEMS], v[SM_ITEMS], rk[SM_ITEMS];
 #pragma unroll
+        for (int i = 0; i < SM_ITEMS; ++i) {  // unconditional loads (index clamped): all in flight before the ranking
+            const uint32_t p = wb + i * 64 + l;
+            k[i] = kin[p < n ? p : 0u];
+            v[i] = vin[p < n ? p : 0u];
+        }
+#pragma unroll
         for (int i = 0; i < SM_ITEMS; ++i) {
             const uint32_t p = wb + i * 64 + l;
             const bool ok = p < n;
-            k[i] = ok ? kin[p] : 0u;
-            v[i] = ok ? vin[p] : 0u;
             const uint32_t d = (k[i] >> shift) & 255u;
             uint64_t m = __ballot(ok);
 #pragma unroll
@@ -182,16 +211,17 @@ __device__ __forceinline__ void small_row_of(const SmallDesc &D, uint32_t s) {
 // (result back in keys/vals), slab starts, bucket bits and window bases in
 // sA.geo (whose static part is set).  False (with Z.status = 1) when the
 // request outgrows its scratch.
-__device__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+__device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
                                   int &s_flag) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
+    const int passes = min((D.key_bits + 7) / 8, SM_MAX_PASSES);
     {
-        const int passes = (D.key_bits + 7) / 8;
+        blk_digit_counts(D.keys, n, passes, P.sort);
         uint32_t *ka = D.keys, *va = D.vals, *kb = D.keys2, *vb = D.vals2;
         for (int p = 0; p < passes; ++p) {
-            blk_sort_pass(ka, va, kb, vb, n, 8 * p, P.sort);
+            blk_sort_pass(ka, va, kb, vb, n, 8 * p, P.sort.dig[p], P.sort);
             uint32_t *x = ka; ka = kb; kb = x;
             x = va; va = vb; vb = x;
         }
@@ -204,18 +234,15 @@ __device__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs 
     }
     __syncthreads();
 
+    // slab starts from the last pass's digit counts: slab j holds the keys
+    // whose top digit (key >> 8 (passes - 1), at most 3 bytes down, inside
+    // the slab field's 27-bit shift) lies in [j, j + 1) << (QBITS - 8 (passes - 1))
     if (t <= B) {
-        uint32_t lo = 0, hi = n;
-        if (t == B) {
-            lo = n;
-        } else {
-            const uint32_t x = (uint32_t)t << QBITS;
-            while (lo < hi) {
-                const uint32_t mid = lo + (hi - lo) / 2;
-                if (D.keys[mid] < x) lo = mid + 1; else hi = mid;
-            }
-        }
-        s_bs[t] = lo;
+        const int top = passes - 1, per = QBITS - 8 * top;
+        const uint32_t dend = min((uint32_t)t << per, 256u);
+        uint32_t lo = 0;
+        for (uint32_t d = 0; d < dend; ++d) lo += P.sort.dig[top][d];
+        s_bs[t] = t == B ? n : lo;
     }
     __syncthreads();
     if (t == 0) {
@@ -252,8 +279,15 @@ __device__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs 
     return true;
 }
 
+// The same, as a call of its own (the one-launch kernel's whole pipeline
+// does not fit its registers with the sort inlined).
+__device__ __noinline__ bool small_sort_layout_call(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P,
+                                                    uint32_t *s_bs, int &s_flag) {
+    return small_sort_layout(D, Z, sA, P, s_bs, s_flag);
+}
+
 // The slab bucket index of the sorted keys, by one workgroup.
-__device__ void small_bucket(const SmallDesc &D, const Geo &g) {
+__device__ __forceinline__ void small_bucket(const SmallDesc &D, const Geo &g) {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t n = (uint32_t)D.src.n;
     for (uint32_t s = t; s < n; s += SM_THREADS) {
@@ -278,7 +312,7 @@ __device__ void small_bucket(const SmallDesc &D, const Geo &g) {
 // Phases a0-a3 of one request by one workgroup (sample, slab keys, sort,
 // slab starts, table, bucket index), leaving its geometry in sA.geo.  False
 // (with Z.status = 1) when the request outgrows its scratch.
-__device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+__device__ __forceinline__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
                              int &s_flag) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
@@ -289,7 +323,7 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
     __syncthreads();
     for (uint32_t i = t; i < n; i += SM_THREADS) small_key_of(D, sA.geo, i);
     __syncthreads();
-    if (!small_sort_layout(D, Z, sA, P, s_bs, s_flag)) return false;
+    if (!small_sort_layout_call(D, Z, sA, P, s_bs, s_flag)) return false;
     for (uint32_t s = t; s < n; s += SM_THREADS) small_row_of(D, s);
     small_bucket(D, sA.geo);
     __syncthreads();
@@ -300,7 +334,7 @@ __device__ bool small_tables(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, 
 // the units' batches; the query arguments completed in A (LDS or device
 // memory) and the unit count in U.  False (with Z.status = 1) when the
 // units outgrow the request's scratch.
-__device__ bool small_units(const SmallDesc &D, SmallResult &Z, QueryArgs &A, ScanSmem &SS, uint64_t &U_out) {
+__device__ __forceinline__ bool small_units(const SmallDesc &D, SmallResult &Z, QueryArgs &A, ScanSmem &SS, uint64_t &U_out) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const uint32_t nb = (n + 63) / 64;
