@@ -81,10 +81,19 @@ __device__ __forceinline__ void blk_scan_array(const T *in, uint64_t *out, uint3
     __syncthreads();
 }
 
+// Global-memory views of the sort's buffers: their loads and stores then
+// compile to global instructions, counted apart from the LDS ones, so that
+// waiting for an LDS result does not also wait for every store in flight
+// (generic pointers give flat instructions, counted with both).
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+__device__ __forceinline__ const g_u32 *as_global(const uint32_t *p) { return (const g_u32 *)p; }
+__device__ __forceinline__ g_u32 *as_global(uint32_t *p) { return (g_u32 *)p; }
+
 // The digit counts of every pass into S.dig, from one read of the keys
 // (they do not depend on the order), SM_UNROLL keys per thread in flight.
 constexpr int SM_UNROLL = 8;
-__device__ __forceinline__ void blk_digit_counts(const uint32_t *keys, uint32_t n, int passes, SortSmem &S) {
+__device__ __forceinline__ void blk_digit_counts(const uint32_t *keys_, uint32_t n, int passes, SortSmem &S) {
+    const g_u32 *keys = as_global(keys_);
     const int t = threadIdx.x;
     for (int x = t; x < SM_MAX_PASSES * 256; x += SM_THREADS) S.dig[x >> 8][x & 255] = 0;
     __syncthreads();
@@ -109,8 +118,11 @@ __device__ __forceinline__ void blk_digit_counts(const uint32_t *keys, uint32_t 
 
 // One stable LSD pass (8-bit digit at `shift`) of n keys with payload;
 // cnt: the digit counts of this pass (S.dig).
-__device__ __forceinline__ void blk_sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n,
-                              int shift, const uint32_t *cnt, SortSmem &S) {
+__device__ __forceinline__ void blk_sort_pass(const uint32_t *kin_, const uint32_t *vin_, uint32_t *kout_,
+                                              uint32_t *vout_, uint32_t n, int shift, const uint32_t *cnt,
+                                              SortSmem &S) {
+    const g_u32 *kin = as_global(kin_), *vin = as_global(vin_);
+    g_u32 *kout = as_global(kout_), *vout = as_global(vout_);
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     if (t < 64) {  // exclusive scan of 256 counts by one wavefront, 4 per lane
         uint32_t c[4], s = 0;
@@ -211,17 +223,17 @@ __device__ __forceinline__ void small_row_of(const SmallDesc &D, uint32_t s) {
 // (result back in keys/vals), slab starts, bucket bits and window bases in
 // sA.geo (whose static part is set).  False (with Z.status = 1) when the
 // request outgrows its scratch.
-__device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P, uint32_t *s_bs,
+__device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, SortSmem &SO, uint32_t *s_bs,
                                   int &s_flag) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
     const int passes = min((D.key_bits + 7) / 8, SM_MAX_PASSES);
     {
-        blk_digit_counts(D.keys, n, passes, P.sort);
+        blk_digit_counts(D.keys, n, passes, SO);
         uint32_t *ka = D.keys, *va = D.vals, *kb = D.keys2, *vb = D.vals2;
         for (int p = 0; p < passes; ++p) {
-            blk_sort_pass(ka, va, kb, vb, n, 8 * p, P.sort.dig[p], P.sort);
+            blk_sort_pass(ka, va, kb, vb, n, 8 * p, SO.dig[p], SO);
             uint32_t *x = ka; ka = kb; kb = x;
             x = va; va = vb; vb = x;
         }
@@ -241,7 +253,7 @@ __device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResul
         const int top = passes - 1, per = QBITS - 8 * top;
         const uint32_t dend = min((uint32_t)t << per, 256u);
         uint32_t lo = 0;
-        for (uint32_t d = 0; d < dend; ++d) lo += P.sort.dig[top][d];
+        for (uint32_t d = 0; d < dend; ++d) lo += SO.dig[top][d];
         s_bs[t] = t == B ? n : lo;
     }
     __syncthreads();
@@ -283,7 +295,7 @@ __device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResul
 // does not fit its registers with the sort inlined).
 __device__ __noinline__ bool small_sort_layout_call(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P,
                                                     uint32_t *s_bs, int &s_flag) {
-    return small_sort_layout(D, Z, sA, P, s_bs, s_flag);
+    return small_sort_layout(D, Z, sA, P.sort, s_bs, s_flag);
 }
 
 // The slab bucket index of the sorted keys, by one workgroup.
@@ -515,8 +527,10 @@ __global__ __launch_bounds__(SP_THREADS) void k_small_keys(const SmallDesc *desc
 // index; the query arguments (the geometry so far) then go to device memory
 // for the next launches, and the status is set
 __global__ __launch_bounds__(SM_THREADS) void k_small_sort(const SmallDesc *descs, SmallResult *results) {
+    // the sort's LDS only (not the one-launch kernel's union of every
+    // phase), so that the workgroup fits on a CU beside other work sooner
     __shared__ QueryArgs sA;
-    __shared__ PhaseSmem P;
+    __shared__ SortSmem P;
     __shared__ uint32_t s_bs[MAX_BANDS + 1];
     __shared__ int s_flag;
     const SmallDesc &D = descs[blockIdx.x];
