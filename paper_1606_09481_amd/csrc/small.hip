@@ -228,7 +228,7 @@ __device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResul
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
-    const int passes = min((D.key_bits + 7) / 8, SM_MAX_PASSES);
+    const int passes = (D.key_bits + 7) / 8;  // 4: QBITS + 1..5 bits
     {
         blk_digit_counts(D.keys, n, passes, SO);
         uint32_t *ka = D.keys, *va = D.vals, *kb = D.keys2, *vb = D.vals2;
@@ -249,6 +249,9 @@ __device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResul
     // slab starts from the last pass's digit counts: slab j holds the keys
     // whose top digit (key >> 8 (passes - 1), at most 3 bytes down, inside
     // the slab field's 27-bit shift) lies in [j, j + 1) << (QBITS - 8 (passes - 1))
+    // (the keys have QBITS + 1..5 bits, so 4 passes and a top digit
+    // (key >> 24) = (slab << 3) | 3 angle bits, j << 3 <= 256 for j <= B)
+    static_assert(QBITS > 24 && QBITS + 5 <= 32 && (MAX_BANDS << (QBITS - 24)) <= 256, "slab starts from the top digit");
     if (t <= B) {
         const int top = passes - 1, per = QBITS - 8 * top;
         const uint32_t dend = min((uint32_t)t << per, 256u);
