@@ -2,7 +2,7 @@
 // the allocation-free entry point).
 //
 // k_small: each workgroup generates one request completely:
-// sample + slab keys, a workgroup-wide stable LSD radix sort, table gather,
+// sample + slab keys, a workgroup-wide stable bucket sort, table gather,
 // slab starts and bucket index, the window plan (plan_batch), batch and unit
 // scans, the count pass (count_unit), the edge scan, an atomic reservation
 // of its slice of the shared output pool, and the emit pass (emit_unit).
@@ -30,21 +30,23 @@ using namespace rhgd;
 
 constexpr int SM_THREADS = 1024;
 constexpr int SM_WAVES = SM_THREADS / 64;
-constexpr int SM_ITEMS = 16;
-constexpr int SM_TILE = SM_THREADS * SM_ITEMS;  // keys ranked per sort step
-
-constexpr int SM_MAX_PASSES = 4;
 struct SortSmem {
-    uint32_t h[256];
-    uint32_t off[256];
-    uint32_t wcnt[SM_WAVES][256];
-    uint32_t dig[SM_MAX_PASSES][256];  // digit counts of every pass
+    uint32_t h[SM_WAVES];  // wavefront totals of the bucket scan
+    uint32_t top[256];     // counts of the keys' top byte (slab << 3 | 3 angle bits)
+};
+// interpolation buckets of the bucket sort: the one-launch kernel's
+// requests (at most 8192 points) and the spread sort's (up to the server's
+// group cutoff, 1.5 points per bucket at 24576)
+constexpr uint32_t SM_BUCKETS_ONE = 8192, SM_BUCKETS_SPREAD = 16384;
+struct SortBucketSmem {
+    SortSmem s;
+    uint32_t bcnt[SM_BUCKETS_ONE];
 };
 struct ScanSmem {
     uint64_t wsum[SM_WAVES];
 };
 union PhaseSmem {
-    SortSmem sort;
+    SortBucketSmem sort;
     CountSmem<0> count0[SM_WAVES];
     CountSmem<1> count1[SM_WAVES];
     EmitSmem emit[SM_WAVES];
@@ -89,13 +91,12 @@ typedef __attribute__((address_space(1))) uint32_t g_u32;
 __device__ __forceinline__ const g_u32 *as_global(const uint32_t *p) { return (const g_u32 *)p; }
 __device__ __forceinline__ g_u32 *as_global(uint32_t *p) { return (g_u32 *)p; }
 
-// The digit counts of every pass into S.dig, from one read of the keys
-// (they do not depend on the order), SM_UNROLL keys per thread in flight.
+// The counts of the keys' top byte into S.top, SM_UNROLL keys per thread in flight.
 constexpr int SM_UNROLL = 8;
-__device__ __forceinline__ void blk_digit_counts(const uint32_t *keys_, uint32_t n, int passes, SortSmem &S) {
+__device__ __forceinline__ void blk_top_counts(const uint32_t *keys_, uint32_t n, SortSmem &S) {
     const g_u32 *keys = as_global(keys_);
     const int t = threadIdx.x;
-    for (int x = t; x < SM_MAX_PASSES * 256; x += SM_THREADS) S.dig[x >> 8][x & 255] = 0;
+    for (int x = t; x < 256; x += SM_THREADS) S.top[x] = 0;
     __syncthreads();
     for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
         uint32_t k[SM_UNROLL];
@@ -105,95 +106,139 @@ __device__ __forceinline__ void blk_digit_counts(const uint32_t *keys_, uint32_t
             k[u] = keys[i < n ? i : 0u];
         }
 #pragma unroll
-        for (int u = 0; u < SM_UNROLL; ++u) {
-            if (base + (uint32_t)u * SM_THREADS < n) {
-#pragma unroll
-                for (int p = 0; p < SM_MAX_PASSES; ++p)
-                    if (p < passes) atomicAdd(&S.dig[p][(k[u] >> (8 * p)) & 255u], 1u);
-            }
-        }
+        for (int u = 0; u < SM_UNROLL; ++u)
+            if (base + (uint32_t)u * SM_THREADS < n) atomicAdd(&S.top[k[u] >> 24], 1u);
     }
     __syncthreads();
 }
 
-// One stable LSD pass (8-bit digit at `shift`) of n keys with payload;
-// cnt: the digit counts of this pass (S.dig).
-__device__ __forceinline__ void blk_sort_pass(const uint32_t *kin_, const uint32_t *vin_, uint32_t *kout_,
-                                              uint32_t *vout_, uint32_t n, int shift, const uint32_t *cnt,
-                                              SortSmem &S) {
-    const g_u32 *kin = as_global(kin_), *vin = as_global(vin_);
-    g_u32 *kout = as_global(kout_), *vout = as_global(vout_);
+// Bucket of a slab key for the bucket sort: its rank estimated from its
+// slab's start and size and its angle (uniform within the slab for sampled
+// points), scaled to nbk buckets.  Non-decreasing in the key, so every key
+// of bucket b is below every key of bucket b + 1 and equal keys share one.
+// (scale = nbk / n in FP32: a rounded product is still non-decreasing in
+// the estimate, and the clamp keeps the last bucket; no integer division)
+__device__ __forceinline__ uint32_t sort_bucket(uint32_t key, const uint32_t *bs, float scale, uint32_t nbk) {
+    const uint32_t j = key >> QBITS, start = bs[j], nj = bs[j + 1] - start;
+    const uint32_t est = start + (uint32_t)(((uint64_t)(key & QMASK) * nj) >> QBITS);  // in [start, start + nj)
+    const uint32_t b = (uint32_t)((float)est * scale);
+    return b < nbk ? b : nbk - 1u;
+}
+
+// Stable sort of the keys with their payload by interpolation buckets, by
+// one workgroup, given the slab starts bs[0..B]: bucket counts and offsets,
+// the pairs scattered into their buckets (keys2, vals2, any order inside a
+// bucket), and each pair written to keys, vals at its bucket's start plus
+// the number of pairs of its bucket below it in (key, payload) order.  With
+// the payload the original position, that is the order a stable sort of the
+// keys gives.  The order holds for any bucket sizes; the cost assumes small
+// buckets, which sampled points give (their angles are uniform within a
+// slab, about Poisson(n / nbk) points per bucket).
+template <uint32_t NBK>
+__device__ __forceinline__ void blk_bucket_sort(const SmallDesc &D, uint32_t n, const uint32_t *bs, SortSmem &S,
+                                                uint32_t *bcnt) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    if (t < 64) {  // exclusive scan of 256 counts by one wavefront, 4 per lane
-        uint32_t c[4], s = 0;
-        for (int k = 0; k < 4; ++k) {
-            c[k] = cnt[4 * t + k];
-            s += c[k];
+    const uint32_t nbk = n < NBK ? n : NBK;
+    const float scale = (float)nbk / (float)n;
+    const g_u32 *keys = as_global(D.keys), *vals = as_global(D.vals);
+    g_u32 *k2 = as_global(D.keys2), *v2 = as_global(D.vals2);
+    for (uint32_t b = t; b < nbk; b += SM_THREADS) bcnt[b] = 0;
+    __syncthreads();
+    for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
+        uint32_t k[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            const uint32_t i = base + (uint32_t)u * SM_THREADS;
+            k[u] = keys[i < n ? i : 0u];
         }
-        const uint32_t ex = wave_incl_scan_u32(s) - s;
-        uint32_t run = ex;
-        for (int k = 0; k < 4; ++k) {
-            S.off[4 * t + k] = run;
-            run += c[k];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            if (base + (uint32_t)u * SM_THREADS < n) atomicAdd(&bcnt[sort_bucket(k[u], bs, scale, nbk)], 1u);
         }
     }
     __syncthreads();
-    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    for (uint32_t base = 0; base < n; base += SM_TILE) {
-        for (int d = l; d < 256; d += 64) S.wcnt[w][d] = 0;
-        __syncthreads();
-        const uint32_t wb = base + (uint32_t)w * (SM_ITEMS * 64);
-        uint32_t k[SM_ITEMS], v[SM_ITEMS], rk[SM_ITEMS];
+    // exclusive offsets: NBK / SM_THREADS consecutive buckets per thread
+    constexpr uint32_t PER = NBK / SM_THREADS;
+    static_assert(NBK % SM_THREADS == 0, "buckets per thread");
+    uint32_t c[PER], sum = 0;
 #pragma unroll
-        for (int i = 0; i < SM_ITEMS; ++i) {  // unconditional loads (index clamped): all in flight before the ranking
-            const uint32_t p = wb + i * 64 + l;
-            k[i] = kin[p < n ? p : 0u];
-            v[i] = vin[p < n ? p : 0u];
-        }
-#pragma unroll
-        for (int i = 0; i < SM_ITEMS; ++i) {
-            const uint32_t p = wb + i * 64 + l;
-            const bool ok = p < n;
-            const uint32_t d = (k[i] >> shift) & 255u;
-            uint64_t m = __ballot(ok);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bb = __ballot(bit);
-                m &= bit ? bb : ~bb;
-            }
-            const uint32_t below = (uint32_t)__popcll(m & lt);
-            const uint32_t prev = S.wcnt[w][d];
-            rk[i] = prev + below;
-            __builtin_amdgcn_wave_barrier();
-            if (ok && below == 0) S.wcnt[w][d] = prev + (uint32_t)__popcll(m);
-            __builtin_amdgcn_wave_barrier();
-        }
-        __syncthreads();
-        if (t < 256) {  // per digit: exclusive prefix over the wavefronts, tile total
-            uint32_t run = 0;
-            for (int q = 0; q < SM_WAVES; ++q) {
-                const uint32_t c = S.wcnt[q][t];
-                S.wcnt[q][t] = run;
-                run += c;
-            }
-            S.h[t] = run;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < SM_ITEMS; ++i) {
-            const uint32_t p = wb + i * 64 + l;
-            if (p < n) {
-                const uint32_t d = (k[i] >> shift) & 255u;
-                const uint32_t dst = S.off[d] + S.wcnt[w][d] + rk[i];
-                kout[dst] = k[i];
-                vout[dst] = v[i];
-            }
-        }
-        __syncthreads();
-        if (t < 256) S.off[t] += S.h[t];
-        __syncthreads();
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t b = (uint32_t)t * PER + q;
+        c[q] = b < nbk ? bcnt[b] : 0u;
+        sum += c[q];
     }
+    const uint32_t incl = wave_incl_scan_u32(sum);
+    if (l == 63) S.h[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int q = 0; q < w; ++q) run += S.h[q];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t b = (uint32_t)t * PER + q;
+        if (b < nbk) bcnt[b] = run;
+        run += c[q];
+    }
+    __syncthreads();
+    // scatter: bcnt[b] advances from the bucket's start to its end
+    for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
+        uint32_t k[SM_UNROLL], v[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            const uint32_t i = base + (uint32_t)u * SM_THREADS, ic = i < n ? i : 0u;
+            k[u] = keys[ic];
+            v[u] = vals[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            if (base + (uint32_t)u * SM_THREADS < n) {
+                const uint32_t pos = atomicAdd(&bcnt[sort_bucket(k[u], bs, scale, nbk)], 1u);
+                k2[pos] = k[u];
+                v2[pos] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    // each pair to its place: its bucket's start plus its rank inside the
+    // bucket; SM_UNROLL pairs per thread, the m-th members of their buckets
+    // loaded together
+    for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
+        uint32_t key[SM_UNROLL], val[SM_UNROLL], st[SM_UNROLL], en[SM_UNROLL], rank[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            const uint32_t p = base + (uint32_t)u * SM_THREADS, pc = p < n ? p : 0u;
+            key[u] = k2[pc];
+            val[u] = v2[pc];
+        }
+        uint32_t most = 0;
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            const uint32_t b = sort_bucket(key[u], bs, scale, nbk);
+            st[u] = b ? bcnt[b - 1] : 0u;
+            en[u] = base + (uint32_t)u * SM_THREADS < n ? bcnt[b] : st[u];
+            rank[u] = 0;
+            most = max(most, en[u] - st[u]);
+        }
+        for (uint32_t m = 0; m < most; ++m) {
+            uint32_t kq[SM_UNROLL], vq[SM_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SM_UNROLL; ++u) {
+                const uint32_t q = st[u] + m < en[u] ? st[u] + m : 0u;
+                kq[u] = k2[q];
+                vq[u] = v2[q];
+            }
+#pragma unroll
+            for (int u = 0; u < SM_UNROLL; ++u)
+                if (st[u] + m < en[u]) rank[u] += (kq[u] < key[u] || (kq[u] == key[u] && vq[u] < val[u])) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            if (base + (uint32_t)u * SM_THREADS < n) {
+                as_global(D.keys)[st[u] + rank[u]] = key[u];
+                as_global(D.vals)[st[u] + rank[u]] = val[u];
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // a0 + a2 of point i: its sample, slab (thresholds of the static geometry
@@ -219,47 +264,32 @@ __device__ __forceinline__ void small_row_of(const SmallDesc &D, uint32_t s) {
     if (D.f32) D.f32[s] = make_float2((float)a, (float)b);
 }
 
-// a3 and the layout, by one workgroup, after the keys: stable LSD radix sort
+// a3 and the layout, by one workgroup, after the keys: stable bucket sort
 // (result back in keys/vals), slab starts, bucket bits and window bases in
 // sA.geo (whose static part is set).  False (with Z.status = 1) when the
 // request outgrows its scratch.
-__device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, SortSmem &SO, uint32_t *s_bs,
-                                  int &s_flag) {
+template <uint32_t NBK>
+__device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, SortSmem &SO,
+                                                  uint32_t *bcnt, uint32_t *s_bs, int &s_flag) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
     const int B = D.geo.B;
-    const int passes = (D.key_bits + 7) / 8;  // 4: QBITS + 1..5 bits
-    {
-        blk_digit_counts(D.keys, n, passes, SO);
-        uint32_t *ka = D.keys, *va = D.vals, *kb = D.keys2, *vb = D.vals2;
-        for (int p = 0; p < passes; ++p) {
-            blk_sort_pass(ka, va, kb, vb, n, 8 * p, SO.dig[p], SO);
-            uint32_t *x = ka; ka = kb; kb = x;
-            x = va; va = vb; vb = x;
-        }
-        if (ka != D.keys) {
-            for (uint32_t i = t; i < n; i += SM_THREADS) {
-                D.keys[i] = ka[i];
-                D.vals[i] = va[i];
-            }
-        }
-    }
-    __syncthreads();
+    blk_top_counts(D.keys, n, SO);
 
-    // slab starts from the last pass's digit counts: slab j holds the keys
-    // whose top digit (key >> 8 (passes - 1), at most 3 bytes down, inside
-    // the slab field's 27-bit shift) lies in [j, j + 1) << (QBITS - 8 (passes - 1))
-    // (the keys have QBITS + 1..5 bits, so 4 passes and a top digit
-    // (key >> 24) = (slab << 3) | 3 angle bits, j << 3 <= 256 for j <= B)
-    static_assert(QBITS > 24 && QBITS + 5 <= 32 && (MAX_BANDS << (QBITS - 24)) <= 256, "slab starts from the top digit");
+    // slab starts from the top-byte counts: the keys have QBITS + 1..5 bits,
+    // so the top byte is (slab << (QBITS - 24)) | the top angle bits, and
+    // slab j holds the keys whose top byte lies in [j, j + 1) << (QBITS - 24)
+    static_assert(QBITS > 24 && QBITS + 5 <= 32 && (MAX_BANDS << (QBITS - 24)) <= 256, "slab starts from the top byte");
     if (t <= B) {
-        const int top = passes - 1, per = QBITS - 8 * top;
-        const uint32_t dend = min((uint32_t)t << per, 256u);
+        const uint32_t dend = min((uint32_t)t << (QBITS - 24), 256u);
         uint32_t lo = 0;
-        for (uint32_t d = 0; d < dend; ++d) lo += SO.dig[top][d];
+        for (uint32_t d = 0; d < dend; ++d) lo += SO.top[d];
         s_bs[t] = t == B ? n : lo;
     }
     __syncthreads();
+
+    blk_bucket_sort<NBK>(D, n, s_bs, SO, bcnt);
+
     if (t == 0) {
         uint64_t wins = 0, btl = 0;
         for (int j = 0; j < B; ++j) {
@@ -294,25 +324,30 @@ __device__ __forceinline__ bool small_sort_layout(const SmallDesc &D, SmallResul
     return true;
 }
 
-// The same, as a call of its own (the one-launch kernel's whole pipeline
-// does not fit its registers with the sort inlined).
-__device__ __noinline__ bool small_sort_layout_call(const SmallDesc &D, SmallResult &Z, QueryArgs &sA, PhaseSmem &P,
-                                                    uint32_t *s_bs, int &s_flag) {
-    return small_sort_layout(D, Z, sA, P.sort, s_bs, s_flag);
-}
-
 // The slab bucket index of the sorted keys, by one workgroup.
 __device__ __forceinline__ void small_bucket(const SmallDesc &D, const Geo &g) {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t n = (uint32_t)D.src.n;
-    for (uint32_t s = t; s < n; s += SM_THREADS) {
-        const uint32_t key = D.keys[s];
-        const int j = (int)(key >> QBITS);
-        const int sh = g.bshift[j];
-        const int64_t b = (int64_t)((key & QMASK) >> sh);
-        const int64_t bp = (s == g.bs[j]) ? -1 : (int64_t)((D.keys[s - 1] & QMASK) >> sh);
-        uint32_t *T = D.btab + g.bto[j];
-        for (int64_t k = bp + 1; k <= b; ++k) T[k] = s;
+    for (uint32_t base = t; base < n; base += SM_UNROLL * SM_THREADS) {
+        uint32_t kc[SM_UNROLL], kp[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {  // unconditional loads (index clamped): all in flight at once
+            const uint32_t s = base + (uint32_t)u * SM_THREADS, sc = s < n ? s : 0u;
+            kc[u] = D.keys[sc];
+            kp[u] = D.keys[sc > 0u ? sc - 1u : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+            const uint32_t s = base + (uint32_t)u * SM_THREADS;
+            if (s < n) {
+                const int j = (int)(kc[u] >> QBITS);
+                const int sh = g.bshift[j];
+                const int64_t b = (int64_t)((kc[u] & QMASK) >> sh);
+                const int64_t bp = (s == g.bs[j]) ? -1 : (int64_t)((kp[u] & QMASK) >> sh);
+                uint32_t *T = D.btab + g.bto[j];
+                for (int64_t k = bp + 1; k <= b; ++k) T[k] = s;
+            }
+        }
     }
     for (int j = w; j < g.B; j += SM_WAVES) {
         const uint32_t nbk = 1u << (QBITS - g.bshift[j]);
@@ -338,7 +373,7 @@ __device__ __forceinline__ bool small_tables(const SmallDesc &D, SmallResult &Z,
     __syncthreads();
     for (uint32_t i = t; i < n; i += SM_THREADS) small_key_of(D, sA.geo, i);
     __syncthreads();
-    if (!small_sort_layout_call(D, Z, sA, P, s_bs, s_flag)) return false;
+    if (!small_sort_layout<SM_BUCKETS_ONE>(D, Z, sA, P.sort.s, P.sort.bcnt, s_bs, s_flag)) return false;
     for (uint32_t s = t; s < n; s += SM_THREADS) small_row_of(D, s);
     small_bucket(D, sA.geo);
     __syncthreads();
@@ -534,6 +569,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_sort(const SmallDesc *desc
     // phase), so that the workgroup fits on a CU beside other work sooner
     __shared__ QueryArgs sA;
     __shared__ SortSmem P;
+    __shared__ uint32_t bcnt[SM_BUCKETS_SPREAD];
     __shared__ uint32_t s_bs[MAX_BANDS + 1];
     __shared__ int s_flag;
     const SmallDesc &D = descs[blockIdx.x];
@@ -543,7 +579,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_sort(const SmallDesc *desc
         s_flag = 0;
     }
     __syncthreads();
-    if (!small_sort_layout(D, Z, sA, P, s_bs, s_flag)) return;
+    if (!small_sort_layout<SM_BUCKETS_SPREAD>(D, Z, sA, P, bcnt, s_bs, s_flag)) return;
     small_bucket(D, sA.geo);
     static_assert(sizeof(QueryArgs) % 4 == 0, "QueryArgs words");
     const uint32_t *src = (const uint32_t *)&sA;
