@@ -241,6 +241,15 @@ __device__ __forceinline__ void blk_bucket_sort(const SmallDesc &D, uint32_t n, 
     __syncthreads();
 }
 
+// The static geometry of a request (n, B, R, K, Kw, FP32 thresholds, c,
+// sinh/exp/reciprocal constants) into the LDS copy, a word per thread.
+__device__ __forceinline__ void geo_to_lds(const Geo &src, Geo &dst) {
+    static_assert(sizeof(Geo) % 4 == 0, "Geo words");
+    const uint32_t *a = (const uint32_t *)&src;
+    uint32_t *b = (uint32_t *)&dst;
+    for (uint32_t k = threadIdx.x; k < sizeof(Geo) / 4; k += SM_THREADS) b[k] = a[k];
+}
+
 // a0 + a2 of point i: its sample, slab (thresholds of the static geometry
 // g) and key, with the payload i.
 __device__ __forceinline__ void small_key_of(const SmallDesc &D, const Geo &g, uint32_t i) {
@@ -366,10 +375,8 @@ __device__ __forceinline__ bool small_tables(const SmallDesc &D, SmallResult &Z,
                              int &s_flag) {
     const int t = threadIdx.x;
     const uint32_t n = (uint32_t)D.src.n;
-    if (t == 0) {
-        sA.geo = D.geo;  // static part: n, B, R, K, Kw, FP32 thresholds, c, sinh/exp/reciprocal constants
-        s_flag = 0;
-    }
+    geo_to_lds(D.geo, sA.geo);
+    if (t == 0) s_flag = 0;
     __syncthreads();
     for (uint32_t i = t; i < n; i += SM_THREADS) small_key_of(D, sA.geo, i);
     __syncthreads();
@@ -574,10 +581,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_sort(const SmallDesc *desc
     __shared__ int s_flag;
     const SmallDesc &D = descs[blockIdx.x];
     SmallResult &Z = results[blockIdx.x];
-    if (threadIdx.x == 0) {
-        sA.geo = D.geo;  // static part, as in small_tables
-        s_flag = 0;
-    }
+    geo_to_lds(D.geo, sA.geo);
+    if (threadIdx.x == 0) s_flag = 0;
     __syncthreads();
     if (!small_sort_layout<SM_BUCKETS_SPREAD>(D, Z, sA, P, bcnt, s_bs, s_flag)) return;
     small_bucket(D, sA.geo);
