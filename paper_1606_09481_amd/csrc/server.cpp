@@ -52,9 +52,10 @@ namespace {
 constexpr int N_LANES = 4;
 constexpr int GROUP_MAX = 128;
 // Largest request taken into a group: measured at fixed arrival rates (6000
-// and 8000 requests/s) between 16384 and 98304 points; larger cutoffs raise
-// the saturation rate but put longer setups into the groups.
-constexpr uint64_t GROUP_N = 24576;
+// and 8000 requests/s) between 24576 and 98304 points with the bucket sort
+// per request; larger cutoffs raise the saturation rate, and p99 at 8000
+// requests/s was lowest at 65536.
+constexpr uint64_t GROUP_N = 65536;
 static_assert(GROUP_MAX <= rhgk::SMALL_GROUP_MAX, "a group fits the spread launch");
 
 // ---------------------------------------------------------------------------

@@ -36,7 +36,7 @@ struct SortSmem {
 };
 // interpolation buckets of the bucket sort: the one-launch kernel's
 // requests (at most 8192 points) and the spread sort's (up to the server's
-// group cutoff, 1.5 points per bucket at 24576)
+// group cutoff, 4 points per bucket at 65536)
 constexpr uint32_t SM_BUCKETS_ONE = 8192, SM_BUCKETS_SPREAD = 16384;
 struct SortBucketSmem {
     SortSmem s;

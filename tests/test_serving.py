@@ -36,7 +36,7 @@ def _edges(g):
     return e, st
 
 
-def _mix(seed, count, n_lo=300, n_hi=24576, large=()):
+def _mix(seed, count, n_lo=300, n_hi=65536, large=()):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
@@ -70,7 +70,7 @@ def _describe(p):
 
 
 def test_mix_equals_alone(ctx):
-    reqs = _mix(11, 60, large=[(40_000, 0.8, 20, rhg.RHG_FP64), (250_000, 1.0, 10, rhg.RHG_FP32_RECHECK)])
+    reqs = _mix(11, 60, large=[(100_000, 0.8, 20, rhg.RHG_FP64), (250_000, 1.0, 10, rhg.RHG_FP32_RECHECK)])
     reqs.append(reqs[5])  # the same request twice in one mix
     srv = rhg.rhg_server_create(0, 4 << 30)
     try:
@@ -159,11 +159,11 @@ def test_request_larger_than_budget_runs_alone(ctx):
 
 def test_group_edges_of_sizes(ctx):
     """Requests at the sizes where batches and the group cutoff change (a few
-    points, one batch and a point more, 24576 and 24577 points: the last
+    points, one batch and a point more, 65536 and 65537 points: the last
     grouped size and the first one that is not), submitted together: each
     equals rhg_generate alone."""
     reqs = [rhg.params(n, 1.0, R=4.0 + 0.5 * k, seed=100 + n) for k, n in enumerate((2, 3, 63, 64, 65, 127, 129))]
-    reqs += [rhg.params(n, 0.9, kbar=12.0, seed=7 + n) for n in (24576, 24577)]
+    reqs += [rhg.params(n, 0.9, kbar=12.0, seed=7 + n) for n in (65536, 65537)]
     srv = rhg.rhg_server_create(0, 4 << 30)
     try:
         tickets = [rhg.rhg_server_submit(srv, p) for p in reqs]
