@@ -19,6 +19,7 @@ using namespace rhgd;
 // runs of pairs and would otherwise put the lanes of an LDS atomic on one
 // bin; one global add per bin and workgroup.
 constexpr int DIR_COPIES = 8;
+constexpr int DIR_UNROLL = 4;
 __global__ __launch_bounds__(256) void k_directed_counts(const int2 *pairs, uint64_t m, uint32_t n, uint32_t *err,
                                                          int passes, uint32_t *counts) {
     __shared__ uint32_t h[DIR_COPIES][4][256];
@@ -27,16 +28,28 @@ __global__ __launch_bounds__(256) void k_directed_counts(const int2 *pairs, uint
         for (int x = 0; x < DIR_COPIES; ++x) h[x][q][threadIdx.x] = 0;
     __syncthreads();
     bool bad = false;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        const int2 p = pairs[e];
-        uint32_t a = (uint32_t)p.x, b = (uint32_t)p.y;
-        if (a >= n || b >= n) {
-            bad = true;
-            a = b = 0u;
+    // DIR_UNROLL pairs per thread in flight at once (one dependent load per
+    // step would leave the read latency-bound)
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += DIR_UNROLL * stride) {
+        int2 p[DIR_UNROLL];
+#pragma unroll
+        for (int u = 0; u < DIR_UNROLL; ++u) {
+            const uint64_t e = e0 + (uint64_t)u * stride;
+            p[u] = pairs[e < m ? e : 0];
         }
-        for (int q = 0; q < passes; ++q) {
-            atomicAdd(&h[c][q][(a >> (8 * q)) & 255u], 1u);
-            atomicAdd(&h[c][q][(b >> (8 * q)) & 255u], 1u);
+#pragma unroll
+        for (int u = 0; u < DIR_UNROLL; ++u) {
+            if (e0 + (uint64_t)u * stride >= m) continue;
+            uint32_t a = (uint32_t)p[u].x, b = (uint32_t)p[u].y;
+            if (a >= n || b >= n) {
+                bad = true;
+                a = b = 0u;
+            }
+            for (int q = 0; q < passes; ++q) {
+                atomicAdd(&h[c][q][(a >> (8 * q)) & 255u], 1u);
+                atomicAdd(&h[c][q][(b >> (8 * q)) & 255u], 1u);
+            }
         }
     }
     if (bad) atomicOr(err, 1u);
